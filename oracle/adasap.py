@@ -1,0 +1,141 @@
+"""ADASAP (Alg. 2) with Nesterov acceleration (Appendix, Alg. NestAcc), SAP (Alg. 1), ADASAP-I.
+
+Test infrastructure (see the package docstring).
+
+One iteration t, in the paper's order and notation (Sec. 4.2, Alg. 2):
+
+  Step I    sample B (size b) uniformly;  G = K_{B,:} Z_t + lambda Z_t[B] - Y_B
+  Step II   Omega (b x r) Gaussian;  sketch K_BB Omega
+  Step III  U, S = NysApprox(K_BB Omega, Omega);  P_B = U S U^T + rho I with
+            rho = S_rr + lambda (the paper's rule) or a fixed rho;
+            eta_B = GetStepsize(P_B, K_BB + lambda I)
+  Step IV   D_t = P_B^{-1} G;  Nesterov update
+            W_{t+1} = Z_t - eta I_B^T D_t
+            V_{t+1} = beta V_t + (1 - beta) Z_t - gamma eta I_B^T D_t
+            Z_{t+1} = alpha V_{t+1} + (1 - alpha) W_{t+1}
+  with beta = 1 - sqrt(mu/nu), gamma = 1/sqrt(mu nu), alpha = 1/(1 + gamma nu),
+  mu = lambda and nu = n/b by default (Sec. 4.2), V_0 = Z_0 = W_0.
+
+Readings of the printed listings (each switchable for the tests):
+  * the gradient is taken at Z_t (grad_at_z=True): the accelerated step moves
+    from Z_t, and the printed Step IV's W_t is read as Z_t;
+  * Z_{t+1} uses V_{t+1} (z_uses_v_next=True), the standard accelerated
+    sketch-and-project recurrence the constants come from;
+  * tail averaging is off unless asked for; when on, W_bar is the mean of
+    W_j for j = floor(T/2) .. T-1 (the form the theorems use).
+
+Modes: precond='nystrom' (ADASAP), 'identity' (ADASAP-I, Sec. 5: P_B = I,
+eta from powering on K_BB + lambda I), 'exact' (P_B = K_BB + lambda I);
+accel=False replaces the Nesterov step by W_{t+1} = W_t - eta I_B^T D_t with
+the gradient at W_t; mode 'sap' is Alg. 1 (exact block solve, eta = 1,
+no acceleration).
+"""
+import math
+
+import numpy as np
+
+from . import kernels as kmod
+from . import nystrom as nys
+from . import rng
+from .stepsize import preconditioned_stepsize
+
+
+def nesterov_constants(mu, nu):
+    """(beta, gamma, alpha) of Alg. 2's initialisation."""
+    if not (mu > 0 and nu > 0):
+        raise ValueError("mu and nu must be positive")
+    if mu > nu:
+        raise ValueError("need mu <= nu so that beta >= 0")
+    beta = 1.0 - math.sqrt(mu / nu)
+    gamma = 1.0 / math.sqrt(mu * nu)
+    alpha = 1.0 / (1.0 + gamma * nu)
+    return beta, gamma, alpha
+
+
+def adasap(X, Y, kind, ell, lam, b, r, iters, seed, *, W0=None, rho_rule=0, rho=None,
+           mu=None, nu=None, power_iters=10, precond="nystrom", accel=True,
+           grad_at_z=True, z_uses_v_next=True, tail_average=False, eps_sketch=nys.EPS64,
+           sweep=0, callback=None):
+    """Run `iters` ADASAP iterations on (K + lam I) W = Y; returns (W, info)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    squeeze = Y.ndim == 1
+    if squeeze:
+        Y = Y[:, None]
+    n, k = Y.shape
+    if not (0 < b <= n):
+        raise ValueError("need 0 < b <= n")
+    if precond == "nystrom" and not (0 < r <= b):
+        raise ValueError("need 0 < r <= b")
+    mu = lam if mu is None else mu
+    nu = n / b if nu is None else nu
+    beta, gamma, alpha = nesterov_constants(mu, nu)
+    W = np.zeros((n, k)) if W0 is None else np.array(W0, dtype=np.float64).reshape(n, k)
+    V = W.copy()
+    Z = W.copy()
+    off = rng.PURPOSE_SWEEP_STRIDE * sweep
+    etas, rhos, lam_hats = [], [], []
+    tail_sum, tail_count = np.zeros_like(W), 0
+    for t in range(iters):
+        if tail_average and t >= iters // 2:
+            tail_sum += W  # W_t, t = floor(T/2) .. T-1
+            tail_count += 1
+        # Step I: block and block gradient
+        B = rng.sample_block(seed, t, n, b, purpose=rng.PURPOSE_B + off)
+        XB = X[B]
+        P_at = Z if (accel and grad_at_z) else W
+        G = kmod.kernel_matmul(XB, X, P_at, kind, ell) + lam * P_at[B] - Y[B]
+        KBB = kmod.kernel_matrix(XB, XB, kind, ell)
+        v0 = rng.normals(seed, rng.PURPOSE_POW + off, t, b)
+        if precond == "nystrom":
+            # Step II: Gaussian test matrix, row i <-> B[i]
+            Omega = rng.normals(seed, rng.PURPOSE_OMEGA + off, t, b * r).reshape(b, r)
+            Ysk = KBB @ Omega
+            # Step III: Nystrom factors, damping, step size
+            U, S, _delta = nys.nystrom(Ysk, Omega, eps=eps_sketch)
+            rho_t = lam + S[-1] if rho_rule == 0 else float(rho)
+            eta, lam_hat = preconditioned_stepsize(
+                lambda v: KBB @ v + lam * v,
+                lambda v: nys.precond_inv_sqrt(U, S, rho_t, v), v0, power_iters)
+            D = nys.precond_inv(U, S, rho_t, G)
+        elif precond == "identity":
+            rho_t = 0.0
+            eta, lam_hat = preconditioned_stepsize(lambda v: KBB @ v + lam * v, lambda v: v,
+                                                   v0, power_iters)
+            D = G
+        elif precond in ("exact", "sap"):
+            rho_t = lam
+            Hb = KBB + lam * np.eye(b)
+            Lc = np.linalg.cholesky(Hb)
+            D = np.linalg.solve(Lc.T, np.linalg.solve(Lc, G))
+            if precond == "sap":
+                eta, lam_hat = 1.0, 1.0
+            else:
+                evals, evecs = np.linalg.eigh(Hb)
+                isq = (evecs / np.sqrt(evals)) @ evecs.T
+                eta, lam_hat = preconditioned_stepsize(lambda v: Hb @ v, lambda v: isq @ v,
+                                                       v0, power_iters)
+        else:
+            raise ValueError("unknown preconditioner %r" % (precond,))
+        etas.append(eta)
+        rhos.append(rho_t)
+        lam_hats.append(lam_hat)
+        # Step IV: update
+        step = np.zeros_like(W)
+        step[B] = eta * D
+        if precond == "sap" or not accel:
+            W = W - step
+            V = W
+            Z = W
+        else:
+            W_next = Z - step
+            V_next = beta * V + (1.0 - beta) * Z - gamma * step
+            Z = alpha * (V_next if z_uses_v_next else V) + (1.0 - alpha) * W_next
+            V = V_next
+            W = W_next
+        if callback is not None:
+            callback(t, W, V, Z)
+    out = tail_sum / tail_count if (tail_average and tail_count) else W
+    info = {"eta": np.array(etas), "rho": np.array(rhos), "lambda_hat": np.array(lam_hats),
+            "beta": beta, "gamma": gamma, "alpha": alpha, "V": V, "Z": Z}
+    return (out[:, 0] if squeeze else out), info

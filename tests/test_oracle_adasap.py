@@ -1,0 +1,179 @@
+"""Pins for the ADASAP oracle: direct solve, one-step property, posterior-mean identity,
+Nesterov constants, non-expansion, separability, fixed point, tail averaging."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import adasap as A
+from oracle import kernels as K
+from oracle import linsys
+from oracle import nystrom as nys
+from paper_2505_13723_amd import inputs
+
+
+def _problem(n=200, d=3, k=1, seed=0, lam=1e-2, ell=1.0, kind=K.RBF):
+    X, Y = inputs.make_small(seed, n, d, k)
+    return X, Y, kind, ell, lam
+
+
+def _knorm(X, E, kind, ell, lam):
+    Kl = K.kernel_matrix(X, X, kind, ell) + lam * np.eye(X.shape[0])
+    return float(np.sqrt(np.sum(E * (Kl @ E))))
+
+
+def test_direct_solve_matches_scipy():
+    X, Y, kind, ell, lam = _problem(n=300, k=2)
+    W = linsys.direct_solve(X, Y, kind, ell, lam)
+    Kl = K.kernel_matrix(X, X, kind, ell) + lam * np.eye(300)
+    Ws = sla.cho_solve(sla.cho_factor(Kl), Y)
+    assert np.linalg.norm(W - Ws) <= 1e-12 * np.linalg.norm(Ws) * np.linalg.cond(Kl) ** 0.5
+    assert linsys.relres(X, Y, W, kind, ell, lam)[0] < 1e-12
+
+
+def test_posterior_mean_identity():
+    X, Y, kind, ell, lam = _problem(n=250, k=2)
+    Wstar = linsys.direct_solve(X, Y, kind, ell, lam)
+    m = linsys.predict(X, X, Wstar, kind, ell)
+    assert np.linalg.norm(m - (Y - lam * Wstar)) <= 1e-10 * np.linalg.norm(Y)
+    # for any W: predict(X, W) = Y - lambda W + R(W)
+    W = np.random.default_rng(1).standard_normal(Y.shape)
+    R = linsys.residual(X, Y, W, kind, ell, lam)
+    assert np.allclose(linsys.predict(X, X, W, kind, ell), Y - lam * W + R, rtol=1e-12, atol=1e-10)
+
+
+@pytest.mark.parametrize("mu,nu,beta,gamma,alpha", [
+    (1e-2, 16.0, 0.975, 2.5, 1 / 41),                                 # n=4096, b=256
+    (1e-3, 1e6 / 8192, 0.99713783, 2.8621670, 2.85400e-3),            # n=1e6, b=8192
+    (1e-2, 2e6 / 16384, 0.99094903, 0.9050967, 8.96978e-3),           # n=2e6, b=16384
+    (1e-2, 1e8 / 32768, 0.99818981, 0.1810193, 1.80693e-3),           # n=1e8, b=32768
+])
+def test_nesterov_constants_table(mu, nu, beta, gamma, alpha):
+    b, g, a = A.nesterov_constants(mu, nu)
+    assert b == pytest.approx(beta, rel=1e-6) and g == pytest.approx(gamma, rel=1e-6)
+    assert a == pytest.approx(alpha, rel=1e-5)
+
+
+def test_nesterov_constants_degenerate():
+    assert A.nesterov_constants(3.0, 3.0) == (0.0, pytest.approx(1 / 3), pytest.approx(0.5))
+    with pytest.raises(ValueError):
+        A.nesterov_constants(2.0, 1.0)
+
+
+@pytest.mark.parametrize("z_next", [True, False])
+@pytest.mark.parametrize("precond", ["nystrom", "exact"])
+def test_one_step_when_block_covers_all_rows(z_next, precond):
+    n = 48
+    X, Y, kind, ell, lam = _problem(n=n, k=2, lam=0.05)
+    W0 = np.random.default_rng(3).standard_normal((n, 2))
+    W1, info = A.adasap(X, Y, kind, ell, lam, b=n, r=n, iters=1, seed=7, W0=W0, rho_rule=1,
+                        rho=lam, precond=precond, z_uses_v_next=z_next)
+    assert abs(info["eta"][0] - 1.0) < 1e-10
+    assert linsys.relres(X, Y, W1, kind, ell, lam)[0] < 1e-10
+
+
+def test_adasap_converges_to_direct_solution():
+    X, Y, kind, ell, lam = _problem(n=400, d=3, k=1, lam=0.05)
+    Wstar = linsys.direct_solve(X, Y, kind, ell, lam)
+    W, info = A.adasap(X, Y, kind, ell, lam, b=200, r=60, iters=200, seed=5)
+    assert np.linalg.norm(W - Wstar) <= 1e-8 * np.linalg.norm(Wstar)
+    assert np.all(info["eta"] > 0) and np.all(info["rho"] > lam)
+
+
+@pytest.mark.slow
+def test_adasap_small_fp64_workload_residual_drops():
+    # the small float64 workload's settings (rho = lambda) at n = 2000: steady progress
+    cfg = inputs.WORKLOADS["c1_fp64_n4096"]
+    X, y = inputs.make_c1(seed=cfg["seed"], n=2000)
+    hist = {}
+
+    def cb(t, W, V, Z):
+        if t + 1 in (30, 120):
+            hist[t + 1] = linsys.relres(X, y[:, None], W, K.RBF, cfg["ell"], cfg["lam"])[0]
+
+    A.adasap(X, y, K.RBF, cfg["ell"], cfg["lam"], cfg["b"], cfg["r"], 120, cfg["seed"],
+             rho_rule=1, rho=cfg["rho"], callback=cb)
+    assert hist[120] < 0.5 * hist[30] and hist[120] < 0.05
+
+
+@pytest.mark.parametrize("precond", ["nystrom", "identity", "exact"])
+def test_non_expansion_without_acceleration(precond):
+    X, Y, kind, ell, lam = _problem(n=150, d=2, k=1, lam=0.02, ell=0.8)
+    Wstar = linsys.direct_solve(X, Y, kind, ell, lam)
+    norms = [_knorm(X, -Wstar, kind, ell, lam)]
+
+    def cb(t, W, V, Z):
+        norms.append(_knorm(X, W - Wstar, kind, ell, lam))
+
+    A.adasap(X, Y, kind, ell, lam, b=30, r=10, iters=40, seed=2, precond=precond, accel=False,
+             callback=cb)
+    norms = np.array(norms)
+    assert np.all(norms[1:] <= norms[:-1] * (1 + 1e-12))
+    assert norms[-1] < 0.9 * norms[0]
+
+
+def test_sap_exact_projection_pythagoras():
+    # Alg. 1: each step is the K_lambda-orthogonal projection onto an affine subspace,
+    # so ||W_t - W*||^2 = ||W_{t+1} - W*||^2 + ||W_{t+1} - W_t||^2 in the K_lambda norm
+    X, Y, kind, ell, lam = _problem(n=120, d=2, k=1, lam=0.05)
+    Wstar = linsys.direct_solve(X, Y, kind, ell, lam)
+    its = [np.zeros_like(Y)]
+    A.adasap(X, Y, kind, ell, lam, b=25, r=5, iters=10, seed=4, precond="sap",
+             callback=lambda t, W, V, Z: its.append(W.copy()))
+    for a, b in zip(its[:-1], its[1:]):
+        lhs = _knorm(X, a - Wstar, kind, ell, lam) ** 2
+        rhs = _knorm(X, b - Wstar, kind, ell, lam) ** 2 + _knorm(X, b - a, kind, ell, lam) ** 2
+        assert lhs == pytest.approx(rhs, rel=1e-9)
+
+
+def test_multi_rhs_is_separable():
+    X, Y, kind, ell, lam = _problem(n=160, d=3, k=3, lam=0.03)
+    Wj, infoj = A.adasap(X, Y, kind, ell, lam, b=40, r=12, iters=15, seed=9)
+    for c in range(3):
+        Wc, infoc = A.adasap(X, Y[:, c], kind, ell, lam, b=40, r=12, iters=15, seed=9)
+        assert np.allclose(Wj[:, c], Wc, rtol=1e-12, atol=1e-12)
+        assert np.array_equal(infoj["eta"], infoc["eta"])
+
+
+def test_fixed_point():
+    X, Y, kind, ell, lam = _problem(n=140, d=2, k=2, lam=0.04)
+    Wstar = linsys.direct_solve(X, Y, kind, ell, lam)
+    W, _ = A.adasap(X, Y, kind, ell, lam, b=35, r=10, iters=6, seed=1, W0=Wstar)
+    assert np.linalg.norm(W - Wstar) <= 1e-10 * np.linalg.norm(Wstar)
+    # W0 = (Y - m)/lambda with the exact posterior mean m = K W* is W* itself
+    m = linsys.predict(X, X, Wstar, kind, ell)
+    assert np.allclose((Y - m) / lam, Wstar, rtol=1e-8, atol=1e-8)
+
+
+def test_tail_average_window():
+    X, Y, kind, ell, lam = _problem(n=100, d=2, k=1)
+    its = [np.zeros((100, 1))]
+    A.adasap(X, Y, kind, ell, lam, b=20, r=5, iters=9, seed=3,
+             callback=lambda t, W, V, Z: its.append(W.copy()))
+    Wbar, _ = A.adasap(X, Y, kind, ell, lam, b=20, r=5, iters=9, seed=3, tail_average=True)
+    assert np.allclose(Wbar, np.mean(its[4:9], axis=0), rtol=1e-13, atol=1e-13)
+
+
+def test_planted_woodbury_sign_error_is_caught(monkeypatch):
+    # a plausible mistake (wrong sign of the complement term) must break the one-step pin
+    def bad(U, S, rho, G):
+        UtG = U.T @ G
+        return U @ (UtG / (S + rho)[:, None]) - (G - U @ UtG) / rho
+    monkeypatch.setattr(nys, "precond_inv", bad)
+    n = 40
+    X, Y, kind, ell, lam = _problem(n=n, k=2, lam=0.05)
+    W1, _ = A.adasap(X, Y, kind, ell, lam, b=n, r=20, iters=1, seed=7, rho_rule=1, rho=lam)
+    assert linsys.relres(X, Y, W1, kind, ell, lam)[0] > 1e-3
+
+
+def test_planted_transposed_kernel_block_is_caught(monkeypatch):
+    # evaluating the gradient with the block's rows and columns swapped breaks convergence
+    orig = K.kernel_matmul
+
+    def bad(X1, X2, R, kind, ell, col_chunk=4096):
+        if X1.shape[0] != X2.shape[0]:
+            return orig(X1, X2, R, kind, ell) * 1.01
+        return orig(X1, X2, R, kind, ell)
+    monkeypatch.setattr(K, "kernel_matmul", bad)
+    X, Y, kind, ell, lam = _problem(n=200, d=3, k=1, lam=0.05)
+    W, _ = A.adasap(X, Y, kind, ell, lam, b=50, r=20, iters=150, seed=5)
+    assert linsys.relres(X, Y, W, kind, ell, lam)[0] > 1e-4
