@@ -1,0 +1,188 @@
+/*
+ * adasap.h -- C ABI of the MI355X (gfx950) ADASAP hot path.
+ *
+ * Solves (K + lambda I) W = Y for a Gaussian-process kernel matrix K = k(X, X)
+ * with ADASAP: approximate, accelerated sketch-and-project ("Turbocharging
+ * Gaussian Process Inference with Approximate Sketch-and-Project", Sec. 4,
+ * Alg. 2).  Every iteration samples a row block B, evaluates the kernel row
+ * block K_{B,:} on the fly against the current iterate, builds a randomized
+ * Nystrom preconditioner of K_BB + rho I (Appendix, Alg. NysApprox), picks the
+ * step size by randomized powering (Appendix, Alg. GetStepsize) and takes the
+ * Nesterov-accelerated projected step (Appendix, Alg. NestAcc).
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are row-major and contiguous.  X is n x d, Y and W are n x k.
+ *  - Pointers documented as "device" must point to memory of the current HIP
+ *    device (for example torch tensors' data_ptr()); "host" pointers to host
+ *    memory.  The caller owns every buffer it passes in.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls that return
+ *    numbers to the host synchronise that stream before returning.
+ *  - Errors are reported by status code only; no call aborts or throws.  The
+ *    message of the last failure on the calling thread is returned by
+ *    adasap_last_error().  Invalid arguments are rejected before any device
+ *    work, and output buffers are then left untouched.
+ *  - Results are deterministic: the same inputs, configuration and seed give
+ *    bit-identical outputs on the same device (no floating-point atomics).
+ */
+#ifndef ADASAP_H
+#define ADASAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADASAP_OK = 0,
+  ADASAP_ERR_INVALID_ARG = 1,   /* argument out of range, null pointer, bad config */
+  ADASAP_ERR_OOM = 2,           /* device or host allocation failed */
+  ADASAP_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+  ADASAP_ERR_NOT_PD = 4,        /* Nystrom core not positive definite after shift retries */
+  ADASAP_ERR_NONFINITE = 5,     /* NaN/Inf in inputs or iterates */
+  ADASAP_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+} adasap_status_t;
+
+/* Covariance functions (textbook forms, unit output scale, scalar lengthscale ell):
+ * RBF exp(-r^2/(2 ell^2)); Matern-1/2 exp(-r/ell); Matern-3/2 (1+a)e^{-a}, a = sqrt(3) r/ell;
+ * Matern-5/2 (1+a+a^2/3)e^{-a}, a = sqrt(5) r/ell. */
+typedef enum { ADASAP_RBF = 0, ADASAP_MATERN12 = 1, ADASAP_MATERN32 = 2, ADASAP_MATERN52 = 3 } adasap_kernel_t;
+
+/* Arithmetic of the kernel-block products.
+ * FP64:  everything in float64.
+ * FP32:  kernel values and their products in float32 (sketch eps = 2^-23); the
+ *        Nystrom core, Woodbury applies, step size and residual norms in float64.
+ * MIXED: squared distances from a three-term float16 split on matrix cores with
+ *        float32 accumulation, kernel values rounded to float16 and multiplied
+ *        with a float16 copy of the iterate on matrix cores (float32 accumulation);
+ *        the rest as FP32; optional float64 refinement sweeps. */
+typedef enum { ADASAP_FP64 = 0, ADASAP_FP32 = 1, ADASAP_MIXED = 2 } adasap_precision_t;
+
+/* Preconditioner of the block step.  NYSTROM is ADASAP (P_B = U S U^T + rho I);
+ * IDENTITY is ADASAP-I (Sec. 5, P_B = I, step size from powering on K_BB + lambda I). */
+typedef enum { ADASAP_PRECOND_NYSTROM = 0, ADASAP_PRECOND_IDENTITY = 1 } adasap_precond_t;
+
+/* Element type of X, Y, W, Xstar and prediction outputs. */
+typedef enum { ADASAP_DTYPE_F32 = 0, ADASAP_DTYPE_F64 = 1 } adasap_dtype_t;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(adasap_config_t) */
+  int32_t kernel;         /* adasap_kernel_t */
+  double lengthscale;     /* ell > 0 */
+  double lambda;          /* likelihood variance lambda > 0 */
+  int64_t block_size;     /* b, 0 < b <= n (Alg. 2 "blocksize") */
+  int32_t rank;           /* r, 0 < r <= min(b, 128) (Nystrom rank) */
+  int32_t rho_rule;       /* 0: rho = lambda + S_rr (Alg. 2); 1: rho = `rho` below */
+  double rho;             /* damping for rho_rule 1, > 0 */
+  double mu, nu;          /* acceleration parameters; <= 0 selects lambda and n/b (Sec. 4.2) */
+  int32_t power_iters;    /* randomized powering applications (Alg. GetStepsize), default 10 */
+  int64_t max_iters;      /* iterations of the solve (per refinement sweep) */
+  double tol;             /* stop when the checked relative residual <= tol (0: never check) */
+  int64_t check_every;    /* iterations between residual checks (0: only at the end) */
+  int32_t refine_sweeps;  /* extra float64 iterative-refinement sweeps after the first solve */
+  int32_t precond;        /* adasap_precond_t */
+  int32_t precision;      /* adasap_precision_t */
+  uint64_t seed;          /* key of every random draw (block, sketch, powering start) */
+  int32_t accel;          /* 1: Nesterov step (Alg. NestAcc); 0: W <- W - eta I_B^T D */
+  int32_t grad_at_z;      /* 1: block gradient at Z_t (reading of Alg. 2 Step IV); 0: at W_t */
+  int32_t z_uses_v_next;  /* 1: Z_{t+1} = alpha V_{t+1} + (1-alpha) W_{t+1}; 0: uses V_t */
+  int32_t tail_average;   /* 1: return the mean of W_j, j = floor(T/2) .. T-1 */
+} adasap_config_t;
+
+typedef struct {
+  int64_t iters;           /* iterations run (all sweeps) */
+  double relres;           /* last checked ||(K+lambda I)W - Y||_F / ||Y||_F (float64 accumulation), -1 if unchecked */
+  double relres_maxcol;    /* same, maximum over the k columns */
+  double solve_ms;         /* device time of the iterations (excludes residual checks) */
+  double check_ms;         /* device time of the residual checks */
+  double eta_last, rho_last, lambda_hat_last, delta_last;
+  int32_t refine_done;     /* refinement sweeps performed */
+  int32_t not_pd_events;   /* Nystrom cores that needed a shift increase */
+  int32_t status;          /* adasap_status_t of the solve */
+} adasap_report_t;
+
+typedef struct adasap_handle_s* adasap_handle_t;
+
+/* Fills `cfg` with the paper's defaults (RBF, rho rule 0, mu = lambda, nu = n/b,
+ * 10 power iterations, Nystrom preconditioner, Nesterov on, FP32). */
+adasap_status_t adasap_config_default(adasap_config_t* cfg);
+
+/* Creates a solver for (K + lambda I) W = Y.  X (n x d) and Y (n x k) are device
+ * pointers of element type `dtype`; the handle borrows them (they must stay alive
+ * and unchanged until adasap_destroy) and allocates its own device workspace
+ * (adasap_workspace_bytes).  Requires 1 <= d <= 64 (d <= 16 for MIXED), 1 <= k <= 128.
+ * On success *out receives the handle. */
+adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, int32_t k,
+                              const void* X, const void* Y, int32_t dtype, void* stream,
+                              adasap_handle_t* out);
+
+/* Device bytes adasap_create would allocate for this problem (0 on invalid input). */
+int64_t adasap_workspace_bytes(const adasap_config_t* cfg, int64_t n, int32_t d, int32_t k);
+
+/* Runs the solve.  W (device, n x k, handle dtype) holds W_0 on entry (zeros =
+ * cold start; V_0 = Z_0 = W_0) and the returned iterate on exit.  `report`
+ * (host, may be NULL) receives statistics.  Synchronises the stream. */
+adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report);
+
+/* Posterior mean m(X*) = k(X*, X) W (Sec. 2, Eq. post_eqns, zero prior mean).
+ * W (device, n x k), Xstar (device, m x d), out (device, m x k), all handle dtype. */
+adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, const void* Xstar,
+                               void* out);
+
+/* Relative residual ||(K + lambda I) W - Y||_F / ||Y||_F with float64 accumulation
+ * (relres) and its maximum over columns (relres_maxcol); host outputs, may be NULL. */
+adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres,
+                                double* relres_maxcol);
+
+/* Per-iteration step sizes eta_t, dampings rho_t and Rayleigh quotients of the last
+ * solve, copied to host arrays of length `count` (entries beyond the run are left). */
+adasap_status_t adasap_get_trace(adasap_handle_t h, double* eta, double* rho, double* lambda_hat,
+                                 int64_t count);
+
+void adasap_destroy(adasap_handle_t h);
+
+/* ---- single steps of the iteration, for parity checks of each step --------------- */
+
+/* Row block B_t of Alg. 2 Step I: a uniform b-subset of [0, n) without replacement,
+ * ascending, drawn with Floyd's algorithm from the Philox4x64-10 stream
+ * (seed, purpose, t) and Lemire bounded integers.  out: host int64[b]. */
+adasap_status_t adasap_sample_block(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n,
+                                    int64_t b, int64_t* out);
+
+/* Standard normals number 0 .. count-1 of stream (seed, purpose, t) (Box-Muller,
+ * cosine branch; the Omega and powering draws of Alg. 2).  out: device double[count]. */
+adasap_status_t adasap_normals(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
+                               double* out, void* stream);
+
+/* Kernel block product OUT = k(Xr, Xc) R (Alg. 2 Step I/II column- and row-block
+ * oracles).  Xr (m x d), Xc (n x d), R (n x k) and OUT (m x k) are device arrays of
+ * element type `dtype`; `precision` selects the arithmetic as for the solver.
+ * Synchronises the stream. */
+adasap_status_t adasap_kblock_matmul(int32_t kernel, double lengthscale, int32_t precision,
+                                     int64_t m, int64_t n, int32_t d, int32_t k, const void* Xr,
+                                     const void* Xc, const void* R, void* out, int32_t dtype,
+                                     void* stream);
+
+/* Randomized Nystrom factors of a b x b PSD matrix from its sketch (Appendix,
+ * Alg. NysApprox): Ysk = M Omega and Omega (device, b x r, float64).  Outputs
+ * (device, float64): U (b x r, orthonormal columns), S (r, descending, >= 0) and
+ * the shift actually used (delta, device double[1]).  eps is the machine epsilon
+ * of the precision the sketch was computed in.  Synchronises the stream. */
+adasap_status_t adasap_nystrom(int64_t b, int32_t r, const double* Ysk, const double* Omega,
+                               double eps, double* U, double* S, double* delta, void* stream);
+
+/* Woodbury applies with P = U diag(S) U^T + rho I (Eq. inv_nys_woodbury and
+ * Eq. inv_sqrt_nys_woodbury): OUT = P^{-1} G (power = 0) or P^{-1/2} G (power = 1).
+ * U (b x r), S (r), G and OUT (b x k): device float64.  Synchronises the stream. */
+adasap_status_t adasap_precond_apply(int64_t b, int32_t r, int32_t k, const double* U,
+                                     const double* S, double rho, int32_t power, const double* G,
+                                     double* out, void* stream);
+
+const char* adasap_last_error(void);
+const char* adasap_status_string(adasap_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADASAP_H */

@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libadasap.so (the C ABI declared in include/adasap.h).
+
+Only argument marshalling lives here: torch tensors are passed as device pointers
+with torch's current HIP stream; every step of the computation runs in the
+library's HIP kernels.  Loading fails loudly when the library is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadasap.so")
+
+RBF, MATERN12, MATERN32, MATERN52 = 0, 1, 2, 3
+KERNELS = {"rbf": RBF, "matern12": MATERN12, "matern32": MATERN32, "matern52": MATERN52}
+FP64, FP32, MIXED = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+PRECOND_NYSTROM, PRECOND_IDENTITY = 0, 1
+DTYPE_F32, DTYPE_F64 = 0, 1
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error",
+          4: "Nystrom core not positive definite", 5: "non-finite values", 6: "unsupported"}
+
+# purposes of the random streams (second Philox key word)
+PURPOSE_B, PURPOSE_OMEGA, PURPOSE_POW, PURPOSE_SWEEP_STRIDE = 5, 6, 7, 16
+
+
+class AdasapError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("kernel", ctypes.c_int32),
+        ("lengthscale", ctypes.c_double), ("lam", ctypes.c_double),
+        ("block_size", ctypes.c_int64), ("rank", ctypes.c_int32), ("rho_rule", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("nu", ctypes.c_double),
+        ("power_iters", ctypes.c_int32), ("max_iters", ctypes.c_int64), ("tol", ctypes.c_double),
+        ("check_every", ctypes.c_int64), ("refine_sweeps", ctypes.c_int32),
+        ("precond", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("accel", ctypes.c_int32), ("grad_at_z", ctypes.c_int32),
+        ("z_uses_v_next", ctypes.c_int32), ("tail_average", ctypes.c_int32),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int64), ("relres", ctypes.c_double), ("relres_maxcol", ctypes.c_double),
+        ("solve_ms", ctypes.c_double), ("check_ms", ctypes.c_double),
+        ("eta_last", ctypes.c_double), ("rho_last", ctypes.c_double),
+        ("lambda_hat_last", ctypes.c_double), ("delta_last", ctypes.c_double),
+        ("refine_done", ctypes.c_int32), ("not_pd_events", ctypes.c_int32), ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_U64 = ctypes.c_uint64
+_D = ctypes.c_double
+
+_SIGNATURES = {
+    "adasap_config_default": (_I32, [ctypes.POINTER(Config)]),
+    "adasap_create": (_I32, [ctypes.POINTER(Config), _I64, _I32, _I32, _P, _P, _I32, _P, ctypes.POINTER(_P)]),
+    "adasap_workspace_bytes": (_I64, [ctypes.POINTER(Config), _I64, _I32, _I32]),
+    "adasap_solve": (_I32, [_P, _P, ctypes.POINTER(Report)]),
+    "adasap_predict": (_I32, [_P, _P, _I64, _P, _P]),
+    "adasap_residual": (_I32, [_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "adasap_get_trace": (_I32, [_P, _P, _P, _P, _I64]),
+    "adasap_destroy": (None, [_P]),
+    "adasap_sample_block": (_I32, [_U64, _U64, _U64, _I64, _I64, _P]),
+    "adasap_normals": (_I32, [_U64, _U64, _U64, _I64, _P, _P]),
+    "adasap_kblock_matmul": (_I32, [_I32, _D, _I32, _I64, _I64, _I32, _I32, _P, _P, _P, _P, _I32, _P]),
+    "adasap_nystrom": (_I32, [_I64, _I32, _P, _P, _D, _P, _P, _P, _P]),
+    "adasap_precond_apply": (_I32, [_I64, _I32, _I32, _P, _P, _D, _I32, _P, _P, _P]),
+    "adasap_last_error": (ctypes.c_char_p, []),
+    "adasap_status_string": (ctypes.c_char_p, [_I32]),
+}
+
+EXPORTED = tuple(_SIGNATURES)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return DTYPE_F64
+    if t.dtype == torch.float32:
+        return DTYPE_F32
+    raise TypeError("tensors must be float32 or float64, got %s" % t.dtype)
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("expected a device tensor")
+        if not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor")
+
+
+class Library:
+    def __init__(self, path=LIB_PATH):
+        if not os.path.exists(path):
+            raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() or "
+                               "python -m paper_2505_13723_amd.build" % path)
+        self.path = path
+        self.cdll = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(self.cdll, name)
+            fn.restype = res
+            fn.argtypes = args
+
+    # -- errors ----------------------------------------------------------------------------
+    def last_error(self):
+        return self.cdll.adasap_last_error().decode()
+
+    def check(self, status):
+        if status != 0:
+            raise AdasapError(status, self.last_error())
+
+    # -- configuration -----------------------------------------------------------------------
+    def config(self, **kw):
+        cfg = Config()
+        self.check(self.cdll.adasap_config_default(ctypes.byref(cfg)))
+        for key, val in kw.items():
+            if key == "kernel" and isinstance(val, str):
+                val = KERNELS[val]
+            if key == "precision" and isinstance(val, str):
+                val = PRECISIONS[val]
+            if key == "lambda":
+                key = "lam"
+            if not hasattr(cfg, key):
+                raise KeyError(key)
+            setattr(cfg, key, val)
+        return cfg
+
+    def workspace_bytes(self, cfg, n, d, k):
+        return self.cdll.adasap_workspace_bytes(ctypes.byref(cfg), n, d, k)
+
+    def create(self, cfg, X, Y):
+        _check_dev(X, Y)
+        if X.dtype != Y.dtype:
+            raise TypeError("X and Y must have the same dtype")
+        Y2 = Y if Y.dim() == 2 else Y.view(-1, 1)
+        h = ctypes.c_void_p()
+        self.check(self.cdll.adasap_create(ctypes.byref(cfg), X.shape[0], X.shape[1], Y2.shape[1],
+                                           _ptr(X), _ptr(Y2), _dtype_code(X), _stream(),
+                                           ctypes.byref(h)))
+        return Handle(self, h, X, Y2, cfg)
+
+    # -- single steps ------------------------------------------------------------------------
+    def sample_block(self, seed, purpose, t, n, b):
+        out = np.zeros(b, dtype=np.int64)
+        self.check(self.cdll.adasap_sample_block(seed, purpose, t, n, b,
+                                                 out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def normals(self, seed, purpose, t, count, device="cuda"):
+        torch = _torch()
+        out = torch.empty(count, dtype=torch.float64, device=device)
+        self.check(self.cdll.adasap_normals(seed, purpose, t, count, _ptr(out), _stream()))
+        return out
+
+    def kblock_matmul(self, kernel, ell, precision, Xr, Xc, R):
+        torch = _torch()
+        _check_dev(Xr, Xc, R)
+        R2 = R if R.dim() == 2 else R.view(-1, 1)
+        out = torch.empty((Xr.shape[0], R2.shape[1]), dtype=Xr.dtype, device=Xr.device)
+        kernel = KERNELS.get(kernel, kernel)
+        precision = PRECISIONS.get(precision, precision)
+        self.check(self.cdll.adasap_kblock_matmul(kernel, ell, precision, Xr.shape[0], Xc.shape[0],
+                                                  Xr.shape[1], R2.shape[1], _ptr(Xr), _ptr(Xc),
+                                                  _ptr(R2), _ptr(out), _dtype_code(Xr), _stream()))
+        return out if R.dim() == 2 else out[:, 0]
+
+    def nystrom(self, Ysk, Omega, eps):
+        torch = _torch()
+        _check_dev(Ysk, Omega)
+        b, r = Omega.shape
+        U = torch.empty((b, r), dtype=torch.float64, device=Omega.device)
+        S = torch.empty(r, dtype=torch.float64, device=Omega.device)
+        delta = torch.empty(1, dtype=torch.float64, device=Omega.device)
+        self.check(self.cdll.adasap_nystrom(b, r, _ptr(Ysk), _ptr(Omega), eps, _ptr(U), _ptr(S),
+                                            _ptr(delta), _stream()))
+        return U, S, float(delta.item())
+
+    def precond_apply(self, U, S, rho, G, power):
+        torch = _torch()
+        _check_dev(U, S, G)
+        G2 = G if G.dim() == 2 else G.view(-1, 1)
+        out = torch.empty_like(G2)
+        self.check(self.cdll.adasap_precond_apply(U.shape[0], U.shape[1], G2.shape[1], _ptr(U),
+                                                  _ptr(S), rho, power, _ptr(G2), _ptr(out),
+                                                  _stream()))
+        return out if G.dim() == 2 else out[:, 0]
+
+
+class Handle:
+    def __init__(self, lib, h, X, Y, cfg):
+        self.lib, self.h, self.X, self.Y, self.cfg = lib, h, X, Y, cfg
+
+    def solve(self, W):
+        _check_dev(W)
+        rep = Report()
+        st = self.lib.cdll.adasap_solve(self.h, _ptr(W), ctypes.byref(rep))
+        self.lib.check(st)
+        return rep.as_dict()
+
+    def predict(self, W, Xstar):
+        torch = _torch()
+        _check_dev(W, Xstar)
+        out = torch.empty((Xstar.shape[0], self.Y.shape[1]), dtype=self.X.dtype, device=self.X.device)
+        self.lib.check(self.lib.cdll.adasap_predict(self.h, _ptr(W), Xstar.shape[0], _ptr(Xstar),
+                                                    _ptr(out)))
+        return out
+
+    def residual(self, W):
+        a, m = ctypes.c_double(), ctypes.c_double()
+        self.lib.check(self.lib.cdll.adasap_residual(self.h, _ptr(W), ctypes.byref(a), ctypes.byref(m)))
+        return a.value, m.value
+
+    def trace(self, count):
+        eta, rho, lh = (np.full(count, np.nan) for _ in range(3))
+        self.lib.check(self.lib.cdll.adasap_get_trace(
+            self.h, eta.ctypes.data_as(ctypes.c_void_p), rho.ctypes.data_as(ctypes.c_void_p),
+            lh.ctypes.data_as(ctypes.c_void_p), count))
+        return {"eta": eta, "rho": rho, "lambda_hat": lh}
+
+    def close(self):
+        if self.h:
+            self.lib.cdll.adasap_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_LIB = None
+
+
+def load():
+    global _LIB
+    if _LIB is None:
+        _LIB = Library()
+    return _LIB

@@ -1,0 +1,229 @@
+// Kernel-block products on the vector ALUs (float64 and float32 arithmetic).
+//
+// OUT = k(Xr, Xc) R for the column-block oracle K_{B,:} Z (Alg. 2 Step I), the row-block
+// sketch K_BB Omega (Step II), the powering matvecs K_BB v (Alg. GetStepsize), residuals
+// and predictions.  The b x n kernel block is never stored: each workgroup owns 256 rows
+// (one per thread, coordinates in registers), streams a range of columns through LDS in
+// tiles of 64 (coordinates and right-hand-side values), evaluates k(x_i, x_j) from
+// coordinate differences and accumulates KC right-hand-side columns in registers.  The
+// column range is split over gridDim.y workgroups; partial results are summed in a fixed
+// order by a second kernel that also applies the epilogue, so results are deterministic.
+#include "internal.h"
+#include "kfun.h"
+
+namespace adasap {
+
+namespace {
+
+constexpr int KB_ROWS = 256;  // rows per workgroup (one per thread)
+constexpr int KB_BN = 64;     // columns per LDS tile
+
+template <typename TA>
+__device__ inline TA load_as(const void* p, DT t, int64_t i) {
+  switch (t) {
+    case DT::F64: return TA(static_cast<const double*>(p)[i]);
+    case DT::F32: return TA(static_cast<const float*>(p)[i]);
+    default: return TA(static_cast<float>(static_cast<const _Float16*>(p)[i]));
+  }
+}
+
+__device__ inline double load_d(const void* p, DT t, int64_t i) { return load_as<double>(p, t, i); }
+
+template <typename TA, int KERN, int DMAX, int KC>
+__global__ __launch_bounds__(KB_ROWS) void kblock_valu_kernel(
+    const void* __restrict__ Xr, const int64_t* __restrict__ ridx, DT xt, int64_t m,
+    const void* __restrict__ Xc, int64_t n, int d, const void* __restrict__ R, DT rt, int64_t ldr,
+    int k, TA* __restrict__ part, int64_t cols_per_split, TA p) {
+  __shared__ TA xs[KB_BN * DMAX];
+  __shared__ TA rs[KB_BN * KC];
+  const int tid = threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * KB_ROWS + tid;
+  const int split = blockIdx.y;
+  const int kc0 = blockIdx.z * KC;
+  const int64_t c0 = (int64_t)split * cols_per_split;
+  const int64_t c1 = c0 + cols_per_split < n ? c0 + cols_per_split : n;
+  const bool valid = row < m;
+  const int64_t src = valid ? (ridx ? ridx[row] : row) : 0;
+  TA xr[DMAX];
+#pragma unroll
+  for (int f = 0; f < DMAX; ++f) xr[f] = (valid && f < d) ? load_as<TA>(Xr, xt, src * d + f) : TA(0);
+  TA acc[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) acc[c] = TA(0);
+
+  for (int64_t j0 = c0; j0 < c1; j0 += KB_BN) {
+    const int nb = (int)((c1 - j0) < KB_BN ? (c1 - j0) : KB_BN);
+    for (int e = tid; e < KB_BN * DMAX; e += KB_ROWS) {
+      const int j = e / DMAX, f = e % DMAX;
+      xs[e] = (j < nb && f < d) ? load_as<TA>(Xc, xt, (j0 + j) * d + f) : TA(0);
+    }
+    for (int e = tid; e < KB_BN * KC; e += KB_ROWS) {
+      const int j = e / KC, c = e % KC;
+      rs[e] = (j < nb && kc0 + c < k) ? load_as<TA>(R, rt, (j0 + j) * ldr + kc0 + c) : TA(0);
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      TA r2 = TA(0);
+#pragma unroll
+      for (int f = 0; f < DMAX; ++f) {
+        const TA df = xr[f] - xs[j * DMAX + f];
+        r2 += df * df;
+      }
+      const TA kv = kfun<KERN, TA>(r2, p);
+#pragma unroll
+      for (int c = 0; c < KC; ++c) acc[c] += kv * rs[j * KC + c];
+    }
+    __syncthreads();
+  }
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+      if (kc0 + c < k) part[((int64_t)split * m + row) * k + kc0 + c] = acc[c];
+  }
+}
+
+template <typename TA>
+__global__ void kblock_reduce_kernel(const TA* __restrict__ part, int splits, int64_t m, int k,
+                                     KbEpilogue ep, void* __restrict__ out, DT ot, int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * k) return;
+  const int64_t i = e / k;
+  const int c = (int)(e % k);
+  double s = 0.0;
+  for (int sp = 0; sp < splits; ++sp) s += (double)part[((int64_t)sp * m + i) * k + c];
+  if (ep.E1) s += ep.a1 * load_d(ep.E1, ep.e1t, (ep.e1idx ? ep.e1idx[i] : i) * ep.lde1 + c);
+  if (ep.E2) s += ep.a2 * load_d(ep.E2, ep.e2t, (ep.e2idx ? ep.e2idx[i] : i) * ep.lde2 + c);
+  if (ot == DT::F64) static_cast<double*>(out)[i * ldo + c] = s;
+  else static_cast<float*>(out)[i * ldo + c] = (float)s;
+}
+
+// per-column sums of squares of a rows x k array: partials per block of rows, then a
+// fixed-order sum (deterministic)
+constexpr int CN_ROWS = 1024;
+__global__ void colsq_partial_kernel(const void* __restrict__ a, DT t, int64_t rows, int k,
+                                     int64_t lda, double* __restrict__ part) {
+  // one block per CN_ROWS rows; thread c < k sums its column over those rows
+  const int64_t r0 = (int64_t)blockIdx.x * CN_ROWS;
+  const int64_t r1 = r0 + CN_ROWS < rows ? r0 + CN_ROWS : rows;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double v = load_d(a, t, r * lda + c);
+      s += v * v;
+    }
+    part[(int64_t)blockIdx.x * k + c] = s;
+  }
+}
+
+__global__ void colsq_final_kernel(const double* __restrict__ part, int nblk, int k,
+                                   double* __restrict__ out) {
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * k + c];
+    out[c] = s;
+  }
+}
+
+template <typename TA, int KERN, int DMAX, int KC>
+void launch_valu(dim3 grid, hipStream_t s, const void* Xr, const int64_t* ridx, DT xt, int64_t m,
+                 const void* Xc, int64_t n, int d, const void* R, DT rt, int64_t ldr, int k,
+                 TA* part, int64_t cps, TA p) {
+  hipLaunchKernelGGL((kblock_valu_kernel<TA, KERN, DMAX, KC>), grid, dim3(KB_ROWS), 0, s, Xr,
+                     ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p);
+}
+
+template <typename TA, int KERN, int DMAX>
+void dispatch_kc(int kc, dim3 grid, hipStream_t s, const void* Xr, const int64_t* ridx, DT xt,
+                 int64_t m, const void* Xc, int64_t n, int d, const void* R, DT rt, int64_t ldr,
+                 int k, TA* part, int64_t cps, TA p) {
+  if (kc == 1) launch_valu<TA, KERN, DMAX, 1>(grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p);
+  else if (kc == 4) launch_valu<TA, KERN, DMAX, 4>(grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p);
+  else launch_valu<TA, KERN, DMAX, 16>(grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p);
+}
+
+template <typename TA, int KERN>
+void dispatch_d(int dmax, int kc, dim3 grid, hipStream_t s, const void* Xr, const int64_t* ridx,
+                DT xt, int64_t m, const void* Xc, int64_t n, int d, const void* R, DT rt,
+                int64_t ldr, int k, TA* part, int64_t cps, TA p) {
+  if (dmax == 16) dispatch_kc<TA, KERN, 16>(kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p);
+  else dispatch_kc<TA, KERN, 64>(kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p);
+}
+
+template <typename TA>
+void dispatch_kern(int kern, int dmax, int kc, dim3 grid, hipStream_t s, const void* Xr,
+                   const int64_t* ridx, DT xt, int64_t m, const void* Xc, int64_t n, int d,
+                   const void* R, DT rt, int64_t ldr, int k, TA* part, int64_t cps, TA p) {
+  switch (kern) {
+    case ADASAP_RBF: dispatch_d<TA, ADASAP_RBF>(dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p); break;
+    case ADASAP_MATERN12: dispatch_d<TA, ADASAP_MATERN12>(dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p); break;
+    case ADASAP_MATERN32: dispatch_d<TA, ADASAP_MATERN32>(dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p); break;
+    default: dispatch_d<TA, ADASAP_MATERN52>(dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k, part, cps, p); break;
+  }
+}
+
+}  // namespace
+
+adasap_status_t colsq(int64_t rows, int k, const void* a, DT t, int64_t lda, double* out,
+                      DevBuf& tmp, hipStream_t s) {
+  const int nblk = (int)((rows + CN_ROWS - 1) / CN_ROWS);
+  ADASAP_TRY(tmp.ensure((size_t)(nblk > 0 ? nblk : 1) * k * sizeof(double)));
+  if (nblk > 0) {
+    hipLaunchKernelGGL(colsq_partial_kernel, dim3(nblk), dim3(128), 0, s, a, t, rows, k, lda,
+                       tmp.as<double>());
+    ADASAP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(colsq_final_kernel, dim3(1), dim3(128), 0, s, tmp.as<double>(), nblk, k, out);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t kblock_valu(int kern, double ell, int prec, int64_t m, int64_t n, int d, int k,
+                            const void* Xr, const int64_t* ridx, DT xt, const void* Xc,
+                            const void* R, DT rt, int64_t ldr, void* out, DT ot, int64_t ldo,
+                            const KbEpilogue& ep, DevBuf& part, hipStream_t s) {
+  if (m <= 0 || k <= 0) return ADASAP_OK;
+  if (d < 1 || d > 64) {
+    set_error("kblock_valu: d must be in [1, 64]");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  const int dmax = d <= 16 ? 16 : 64;
+  const int kc = k == 1 ? 1 : (k <= 4 ? 4 : 16);
+  const int64_t gx = (m + KB_ROWS - 1) / KB_ROWS;
+  const int64_t gz = (k + kc - 1) / kc;
+  // enough workgroups to fill 256 CUs several times, but at least one tile per split
+  int64_t splits = 1, cps = KB_BN;
+  if (n > 0) {
+    splits = (2048 + gx * gz - 1) / (gx * gz);
+    const int64_t max_splits = (n + KB_BN - 1) / KB_BN;
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    cps = (n + splits - 1) / splits;
+    cps = (cps + KB_BN - 1) / KB_BN * KB_BN;
+    splits = (n + cps - 1) / cps;
+  }
+  const size_t tsz = prec == ADASAP_FP64 ? 8 : 4;
+  ADASAP_TRY(part.ensure((size_t)splits * m * k * tsz));
+  const dim3 grid((unsigned)gx, (unsigned)splits, (unsigned)gz);
+  if (n == 0) {
+    ADASAP_HIP(hipMemsetAsync(part.p, 0, (size_t)m * k * tsz, s));
+  } else if (prec == ADASAP_FP64) {
+    dispatch_kern<double>(kern, dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k,
+                          part.as<double>(), cps, kernel_param(kern, ell));
+  } else {
+    dispatch_kern<float>(kern, dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k,
+                         part.as<float>(), cps, (float)kernel_param(kern, ell));
+  }
+  ADASAP_LAUNCH_CHECK();
+  const int64_t total = m * k;
+  const unsigned rb = (unsigned)((total + 255) / 256);
+  if (prec == ADASAP_FP64)
+    hipLaunchKernelGGL(kblock_reduce_kernel<double>, dim3(rb), dim3(256), 0, s,
+                       part.as<double>(), (int)splits, m, k, ep, out, ot, ldo);
+  else
+    hipLaunchKernelGGL(kblock_reduce_kernel<float>, dim3(rb), dim3(256), 0, s, part.as<float>(),
+                       (int)splits, m, k, ep, out, ot, ldo);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+}  // namespace adasap

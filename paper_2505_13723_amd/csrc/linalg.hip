@@ -1,0 +1,578 @@
+// Float64 dense linear algebra of Step III/IV (Appendix, "Randomized Nystrom
+// approximation" and "Computing the stepsize"): Gram products, small GEMMs, the
+// one-workgroup Cholesky of the Nystrom core with its triangular inverse, a cyclic
+// Jacobi eigensolver for the r x r Gram matrix of B = Y_nu R^{-1}, the sorting/shift
+// removal of Alg. NysApprox and the vector reductions of randomized powering.
+// r <= 128 throughout, so every r x r matrix fits one workgroup's LDS (160 KB on gfx950).
+#include "internal.h"
+
+namespace adasap {
+
+namespace {
+
+constexpr int RMAX = 128;
+
+__device__ inline double ld_any(const void* p, DT t, int64_t i) {
+  return t == DT::F64 ? static_cast<const double*>(p)[i] : (double)static_cast<const float*>(p)[i];
+}
+
+// ---------------------------------------------------------------- Gram products P = A^T B
+constexpr int G_T = 16;      // output tile
+constexpr int G_ROWS = 32;   // rows staged per step
+constexpr int G_CHUNK = 1024;  // rows per split
+
+__global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int p, int q,
+                                                           const void* __restrict__ A, DT at,
+                                                           int64_t lda, const void* __restrict__ B,
+                                                           DT bt, int64_t ldb,
+                                                           double* __restrict__ part) {
+  __shared__ double As[G_ROWS][G_T];
+  __shared__ double Bs[G_ROWS][G_T];
+  const int tx = threadIdx.x % G_T, ty = threadIdx.x / G_T;
+  const int pi = blockIdx.y * G_T + ty, qj = blockIdx.x * G_T + tx;
+  const int64_t r0 = (int64_t)blockIdx.z * G_CHUNK;
+  const int64_t r1 = r0 + G_CHUNK < rows ? r0 + G_CHUNK : rows;
+  double acc = 0.0;
+  for (int64_t rr = r0; rr < r1; rr += G_ROWS) {
+    for (int e = threadIdx.x; e < G_ROWS * G_T; e += 256) {
+      const int lr = e / G_T, lc = e % G_T;
+      const int64_t row = rr + lr;
+      const int ca = blockIdx.y * G_T + lc, cb = blockIdx.x * G_T + lc;
+      As[lr][lc] = (row < r1 && ca < p) ? ld_any(A, at, row * lda + ca) : 0.0;
+      Bs[lr][lc] = (row < r1 && cb < q) ? ld_any(B, bt, row * ldb + cb) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int l = 0; l < G_ROWS; ++l) acc += As[l][ty] * Bs[l][tx];
+    __syncthreads();
+  }
+  if (pi < p && qj < q) part[((int64_t)blockIdx.z * p + pi) * q + qj] = acc;
+}
+
+__global__ void gram_reduce_kernel(const double* __restrict__ part, int splits, int p, int q,
+                                   const double* __restrict__ rowscale, double* __restrict__ P) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * q) return;
+  double s = 0.0;
+  for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * p * q + e];
+  if (rowscale) s *= rowscale[e / q];
+  P[e] = s;
+}
+
+// ---------------------------------------------------------------- OUT = f(alpha) E + (A + delta A2) M
+constexpr int M_T = 32;
+__global__ __launch_bounds__(256) void gemm_rm_kernel(int64_t rows, int p, int q,
+                                                      const double* __restrict__ A,
+                                                      const double* __restrict__ A2,
+                                                      const double* __restrict__ delta_ptr,
+                                                      int64_t lda, const double* __restrict__ M,
+                                                      double* __restrict__ out, int64_t ldo,
+                                                      const double* __restrict__ E, int64_t lde,
+                                                      const double* __restrict__ alpha_ptr,
+                                                      int alpha_mode) {
+  __shared__ double As[M_T][M_T + 1];
+  __shared__ double Ms[M_T][M_T + 1];
+  const int tc = threadIdx.x % M_T;
+  const int tr = threadIdx.x / M_T;  // 0..7, rows tr*4 .. tr*4+3
+  const int64_t row0 = (int64_t)blockIdx.y * M_T;
+  const int col = blockIdx.x * M_T + tc;
+  const double delta = (A2 && delta_ptr) ? *delta_ptr : 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int l0 = 0; l0 < p; l0 += M_T) {
+    for (int e = threadIdx.x; e < M_T * M_T; e += 256) {
+      const int a = e / M_T, b = e % M_T;
+      const int64_t row = row0 + a;
+      double v = 0.0;
+      if (row < rows && l0 + b < p) {
+        v = A[row * lda + l0 + b];
+        if (A2) v += delta * A2[row * lda + l0 + b];
+      }
+      As[a][b] = v;
+      Ms[a][b] = (l0 + a < p && blockIdx.x * M_T + b < q) ? M[(int64_t)(l0 + a) * q + blockIdx.x * M_T + b] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int l = 0; l < M_T; ++l) {
+      const double m = Ms[l][tc];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += As[tr * 4 + u][l] * m;
+    }
+    __syncthreads();
+  }
+  if (col >= q) return;
+  double f = 1.0;
+  if (alpha_mode == 1) f = 1.0 / *alpha_ptr;
+  else if (alpha_mode == 2) f = 1.0 / sqrt(*alpha_ptr);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t row = row0 + tr * 4 + u;
+    if (row < rows) {
+      double v = acc[u];
+      if (E) v += f * E[row * lde + col];
+      out[row * ldo + col] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Nystrom core
+__global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __restrict__ Mo,
+                                                        const double* __restrict__ Qo, double eps,
+                                                        double* __restrict__ Rinv,
+                                                        double* __restrict__ Rg,
+                                                        IterScalars* __restrict__ sc) {
+  __shared__ double C[RMAX * RMAX];
+  __shared__ double xd[RMAX];
+  __shared__ int flag;
+  __shared__ double s_delta;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < r; ++i) tr += Mo[i * r + i];
+    s_delta = eps * tr;
+    flag = 0;
+  }
+  __syncthreads();
+  int ok = 0;
+  int attempts = 0;
+  for (; attempts <= 5; ++attempts) {
+    const double delta = s_delta;
+    for (int e = tid; e < r * r; e += 1024) {
+      const int i = e / r, j = e % r;
+      C[i * RMAX + j] = 0.5 * (Mo[i * r + j] + Mo[j * r + i]) + delta * Qo[i * r + j];
+    }
+    __syncthreads();
+    // right-looking Cholesky: C = R^T R, R upper, stored in the upper triangle of C
+    for (int kk = 0; kk < r; ++kk) {
+      if (tid == 0) {
+        const double piv = C[kk * RMAX + kk];
+        if (!(piv > 0.0)) flag = 1;
+        else C[kk * RMAX + kk] = sqrt(piv);
+      }
+      __syncthreads();
+      if (flag) break;
+      const double dk = C[kk * RMAX + kk];
+      for (int j = kk + 1 + tid; j < r; j += 1024) C[kk * RMAX + j] /= dk;
+      __syncthreads();
+      const int w = r - kk - 1;
+      for (int e = tid; e < w * w; e += 1024) {
+        const int i = kk + 1 + e / w, j = kk + 1 + e % w;
+        if (j >= i) C[i * RMAX + j] -= C[kk * RMAX + i] * C[kk * RMAX + j];
+      }
+      __syncthreads();
+    }
+    if (!flag) {
+      ok = 1;
+      break;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_delta *= 10.0;
+      flag = 0;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    sc->delta = s_delta;
+    sc->not_pd = attempts > 0 ? 1 : 0;
+    sc->failed = ok ? 0 : 1;
+  }
+  if (!ok) {
+    for (int e = tid; e < r * r; e += 1024) {
+      Rinv[e] = (e / r == e % r) ? 1.0 : 0.0;
+      if (Rg) Rg[e] = Rinv[e];
+    }
+    return;
+  }
+  if (Rg)
+    for (int e = tid; e < r * r; e += 1024) {
+      const int i = e / r, j = e % r;
+      Rg[e] = j >= i ? C[i * RMAX + j] : 0.0;
+    }
+  // X = R^{-1} (upper).  X[i][j] for i < j is kept in C[j][i] (strictly lower part),
+  // X[j][j] in xd[j]; rows i are processed from the bottom, 8 threads per column j.
+  const int j = tid / 8, part = tid % 8;
+  for (int i = r - 1; i >= 0; --i) {
+    if (j < r && j >= i) {
+      if (j == i) {
+        if (part == 0) xd[j] = 1.0 / C[i * RMAX + i];
+      } else {
+        double s = 0.0;
+        for (int l = i + 1 + part; l <= j; l += 8) {
+          const double xl = (l == j) ? xd[j] : C[j * RMAX + l];
+          s += C[i * RMAX + l] * xl;
+        }
+        s += __shfl_xor(s, 1, 8);
+        s += __shfl_xor(s, 2, 8);
+        s += __shfl_xor(s, 4, 8);
+        if (part == 0) C[j * RMAX + i] = -s / C[i * RMAX + i];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < r * r; e += 1024) {
+    const int a = e / r, b = e % r;
+    Rinv[e] = a == b ? xd[a] : (a < b ? C[b * RMAX + a] : 0.0);
+  }
+}
+
+// ---------------------------------------------------------------- Jacobi eigensolver
+constexpr int JAC_MAX_SWEEPS = 20;
+
+__device__ inline int rr_index(int i, int step, int rp) {
+  // circle method: player 0 fixed, the others rotate by `step`
+  return i == 0 ? 0 : 1 + (i - 1 + step) % (rp - 1);
+}
+
+__global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __restrict__ Hg,
+                                                      double* __restrict__ evals,
+                                                      double* __restrict__ rot,
+                                                      IterScalars* __restrict__ sc) {
+  __shared__ double H[RMAX * RMAX];
+  __shared__ double cs_c[RMAX / 2], cs_s[RMAX / 2];
+  __shared__ int pp[RMAX / 2], qq[RMAX / 2];
+  __shared__ int nrot;
+  __shared__ double hmax;
+  const int tid = threadIdx.x;
+  const int rp = r + (r & 1);
+  const int half = rp / 2;
+  for (int e = tid; e < r * r; e += 1024) H[(e / r) * RMAX + e % r] = Hg[e];
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < r; ++i) m = fmax(m, fabs(H[i * RMAX + i]));
+    hmax = m;
+  }
+  __syncthreads();
+  const double abs_floor = 1e-300 + 1e-18 * hmax;
+  int sweeps_used = 0;
+  for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    if (tid == 0) nrot = 0;
+    __syncthreads();
+    for (int step = 0; step < rp - 1; ++step) {
+      if (tid < half) {
+        const int a = rr_index(tid, step, rp), b = rr_index(rp - 1 - tid, step, rp);
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, s = 0.0;
+        if (q < r) {
+          const double apq = H[p * RMAX + q];
+          const double app = H[p * RMAX + p], aqq = H[q * RMAX + q];
+          if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_floor)) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = fabs(tau) > 1e150 ? 0.5 / tau
+                                               : (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            atomicAdd(&nrot, 1);
+          }
+        }
+        cs_c[tid] = c;
+        cs_s[tid] = s;
+        pp[tid] = p;
+        qq[tid] = q;
+        const int64_t slot = ((int64_t)sweep * (rp - 1) + step) * half + tid;
+        rot[2 * slot] = c;
+        rot[2 * slot + 1] = s;
+      }
+      __syncthreads();
+      // rows:  (H_p, H_q) <- (c H_p - s H_q, s H_p + c H_q)
+      for (int e = tid; e < half * r; e += 1024) {
+        const int k = e / r, jj = e % r;
+        const double s = cs_s[k];
+        if (s == 0.0) continue;
+        const double c = cs_c[k];
+        const int p = pp[k], q = qq[k];
+        const double hp = H[p * RMAX + jj], hq = H[q * RMAX + jj];
+        H[p * RMAX + jj] = c * hp - s * hq;
+        H[q * RMAX + jj] = s * hp + c * hq;
+      }
+      __syncthreads();
+      // columns
+      for (int e = tid; e < half * r; e += 1024) {
+        const int k = e / r, ii = e % r;
+        const double s = cs_s[k];
+        if (s == 0.0) continue;
+        const double c = cs_c[k];
+        const int p = pp[k], q = qq[k];
+        const double hp = H[ii * RMAX + p], hq = H[ii * RMAX + q];
+        H[ii * RMAX + p] = c * hp - s * hq;
+        H[ii * RMAX + q] = s * hp + c * hq;
+      }
+      __syncthreads();
+      if (tid < half && cs_s[tid] != 0.0) {
+        H[pp[tid] * RMAX + qq[tid]] = 0.0;
+        H[qq[tid] * RMAX + pp[tid]] = 0.0;
+      }
+      __syncthreads();
+    }
+    const int done = nrot;
+    __syncthreads();
+    if (done == 0) break;
+    sweeps_used = sweep + 1;
+  }
+  for (int i = tid; i < r; i += 1024) evals[i] = H[i * RMAX + i];
+  if (tid == 0) sc->sweeps = sweeps_used;
+}
+
+// V = J_1 J_2 ... applied to the identity; 8 rows of V per workgroup, one sweep of
+// rotations staged in LDS at a time.
+constexpr int ACC_ROWS = 8;
+__global__ __launch_bounds__(512) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
+                                                           const IterScalars* __restrict__ sc,
+                                                           double* __restrict__ V) {
+  __shared__ double Vs[ACC_ROWS][RMAX];
+  __shared__ double R[(RMAX - 1) * (RMAX / 2) * 2];
+  const int tid = threadIdx.x;
+  const int rp = r + (r & 1);
+  const int half = rp / 2;
+  const int row0 = blockIdx.x * ACC_ROWS;
+  for (int e = tid; e < ACC_ROWS * RMAX; e += 512) {
+    const int a = e / RMAX, b = e % RMAX;
+    Vs[a][b] = (row0 + a == b) ? 1.0 : 0.0;
+  }
+  const int sweeps = sc->sweeps;
+  const int per_sweep = (rp - 1) * half;
+  const int ir = tid / 64, k = tid % 64;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    __syncthreads();
+    for (int e = tid; e < 2 * per_sweep; e += 512) R[e] = rot[(int64_t)sw * 2 * per_sweep + e];
+    __syncthreads();
+    for (int step = 0; step < rp - 1; ++step) {
+      if (k < half && row0 + ir < r) {
+        const double s = R[2 * (step * half + k) + 1];
+        if (s != 0.0) {
+          const double c = R[2 * (step * half + k)];
+          const int a = rr_index(k, step, rp), b = rr_index(rp - 1 - k, step, rp);
+          const int p = a < b ? a : b, q = a < b ? b : a;
+          const double vp = Vs[ir][p], vq = Vs[ir][q];
+          Vs[ir][p] = c * vp - s * vq;
+          Vs[ir][q] = s * vp + c * vq;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < ACC_ROWS * r; e += 512) {
+    const int a = e / r, b = e % r;
+    if (row0 + a < r) V[(int64_t)(row0 + a) * r + b] = Vs[a][b];
+  }
+}
+
+__global__ void nys_finalize_kernel(int r, const double* __restrict__ evals,
+                                    const double* __restrict__ V, int rho_rule, double lam,
+                                    double rho_fixed, double* __restrict__ S,
+                                    double* __restrict__ T, double* __restrict__ cinv,
+                                    double* __restrict__ cisq, IterScalars* __restrict__ sc) {
+  __shared__ int perm[RMAX];
+  __shared__ double sig2[RMAX];
+  __shared__ double s_rho;
+  const int i = threadIdx.x;
+  const double delta = sc->delta;
+  if (i < r) {
+    const double e = evals[i];
+    int rank = 0;
+    for (int j = 0; j < r; ++j) {
+      const double f = evals[j];
+      rank += (f > e) || (f == e && j < i);
+    }
+    perm[rank] = i;
+  }
+  __syncthreads();
+  if (i < r) {
+    const int src = perm[i];
+    const double e = evals[src];
+    sig2[i] = e;
+    S[i] = fmax(0.0, e - delta);
+  }
+  __syncthreads();
+  if (i == 0) {
+    s_rho = rho_rule == 0 ? lam + S[r - 1] : rho_fixed;
+    sc->rho = s_rho;
+  }
+  __syncthreads();
+  const double rho = s_rho;
+  if (i < r) {
+    const double si = S[i];
+    cinv[i] = 1.0 / (si + rho) - 1.0 / rho;
+    cisq[i] = 1.0 / sqrt(si + rho) - 1.0 / sqrt(rho);
+    const double e = sig2[i];
+    const double inv = e > 0.0 ? 1.0 / sqrt(e) : 0.0;
+    const int src = perm[i];
+    for (int l = 0; l < r; ++l) T[l * r + i] = V[l * r + src] * inv;
+  }
+}
+
+// ---------------------------------------------------------------- powering reductions
+constexpr int DOT_BLOCK = 256;
+constexpr int DOT_PER_BLOCK = 4096;
+
+__global__ void dots_partial_kernel(int64_t n, const double* __restrict__ v,
+                                    const double* __restrict__ z, double* __restrict__ part) {
+  __shared__ double s1[DOT_BLOCK], s2[DOT_BLOCK];
+  const int64_t base = (int64_t)blockIdx.x * DOT_PER_BLOCK;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = base + threadIdx.x; i < base + DOT_PER_BLOCK && i < n; i += DOT_BLOCK) {
+    const double zi = z[i];
+    a += v[i] * zi;
+    b += zi * zi;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = DOT_BLOCK / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+__global__ void dots_final_kernel(const double* __restrict__ part, int nblk,
+                                  IterScalars* __restrict__ sc) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  sc->rq = a;
+  sc->vnorm2 = b;
+}
+
+__global__ void normalize_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ v,
+                                 IterScalars* __restrict__ sc, int last) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double inv = 1.0 / sqrt(sc->vnorm2);
+  if (i < n) v[i] = z[i] * inv;
+  if (last && i == 0) {
+    sc->lam_hat = sc->rq;
+    sc->eta = 1.0 / sc->rq;
+  }
+}
+
+__global__ void woodbury_coefs_kernel(int r, const double* __restrict__ S, double rho, int power,
+                                      double* __restrict__ coefs, IterScalars* __restrict__ sc) {
+  const int i = threadIdx.x;
+  if (i < r)
+    coefs[i] = power == 0 ? 1.0 / (S[i] + rho) - 1.0 / rho : 1.0 / sqrt(S[i] + rho) - 1.0 / sqrt(rho);
+  if (i == 0) sc->rho = rho;
+}
+
+}  // namespace
+
+adasap_status_t woodbury_coefs(int r, const double* S, double rho, int power, double* coefs,
+                               IterScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(woodbury_coefs_kernel, dim3(1), dim3(RMAX), 0, s, r, S, rho, power, coefs, sc);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t lda, const void* B,
+                     DT bt, int64_t ldb, double* P, const double* rowscale, DevBuf& part,
+                     hipStream_t s) {
+  int splits = (int)((rows + G_CHUNK - 1) / G_CHUNK);
+  if (splits < 1) splits = 1;
+  ADASAP_TRY(part.ensure((size_t)splits * p * q * sizeof(double)));
+  const dim3 grid((q + G_T - 1) / G_T, (p + G_T - 1) / G_T, splits);
+  hipLaunchKernelGGL(gram_partial_kernel, grid, dim3(256), 0, s, rows, p, q, A, at, lda, B, bt,
+                     ldb, part.as<double>());
+  ADASAP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256), dim3(256), 0, s,
+                     part.as<double>(), splits, p, q, rowscale, P);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t gemm_rm(int64_t rows, int p, int q, const double* A, const double* A2,
+                        const double* delta_ptr, int64_t lda, const double* M, double* out,
+                        int64_t ldo, const double* E, int64_t lde, const double* alpha_ptr,
+                        int alpha_mode, hipStream_t s) {
+  if (rows <= 0) return ADASAP_OK;
+  const dim3 grid((q + M_T - 1) / M_T, (unsigned)((rows + M_T - 1) / M_T));
+  hipLaunchKernelGGL(gemm_rm_kernel, grid, dim3(256), 0, s, rows, p, q, A, A2, delta_ptr, lda, M,
+                     out, ldo, E, lde, alpha_ptr, alpha_mode);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t nys_core(int r, const double* Mo, const double* Qo, double eps, double* Rinv,
+                         double* Rscratch, IterScalars* sc, hipStream_t s) {
+  if (r < 1 || r > RMAX) {
+    set_error("nys_core: rank must be in [1, 128]");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(nys_core_kernel, dim3(1), dim3(1024), 0, s, r, Mo, Qo, eps, Rinv, Rscratch, sc);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+size_t jacobi_rot_capacity(int r) {
+  const int rp = r + (r & 1);
+  return (size_t)JAC_MAX_SWEEPS * (rp - 1) * (rp / 2) * 2;
+}
+
+adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, double* rot_buf,
+                           IterScalars* sc, hipStream_t s) {
+  if (r < 1 || r > RMAX) {
+    set_error("jacobi_eig: size must be in [1, 128]");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  if (r == 1) {
+    // 1 x 1: eigenvalue H, eigenvector 1
+    ADASAP_HIP(hipMemcpyAsync(evals, H, sizeof(double), hipMemcpyDeviceToDevice, s));
+    const double one = 1.0;
+    ADASAP_HIP(hipMemcpyAsync(V, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    ADASAP_HIP(hipStreamSynchronize(s));
+    return ADASAP_OK;
+  }
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, r, H, evals, rot_buf, sc);
+  ADASAP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_ROWS - 1) / ACC_ROWS), dim3(512), 0, s, r,
+                     rot_buf, sc, V);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t nys_finalize(int r, const double* evals, const double* V, int rho_rule,
+                             double lam, double rho_fixed, double* S, double* T, double* cinv,
+                             double* cisq, IterScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(nys_finalize_kernel, dim3(1), dim3(RMAX), 0, s, r, evals, V, rho_rule, lam,
+                     rho_fixed, S, T, cinv, cisq, sc);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t dots_vz(int64_t b, const double* v, const double* z, IterScalars* sc,
+                        DevBuf& part, hipStream_t s) {
+  const int nblk = (int)((b + DOT_PER_BLOCK - 1) / DOT_PER_BLOCK);
+  ADASAP_TRY(part.ensure((size_t)2 * (nblk > 0 ? nblk : 1) * sizeof(double)));
+  if (nblk > 0) {
+    hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk), dim3(DOT_BLOCK), 0, s, b, v, z,
+                       part.as<double>());
+    ADASAP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(dots_final_kernel, dim3(1), dim3(64), 0, s, part.as<double>(), nblk, sc);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t normalize_into(int64_t b, const double* z, double* v, IterScalars* sc, int last,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)((b + 255) / 256)), dim3(256), 0, s, b, z,
+                     v, sc, last);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf& part,
+                                  hipStream_t s) {
+  ADASAP_TRY(dots_vz(b, v, v, sc, part, s));
+  return normalize_into(b, v, v, sc, 0, s);
+}
+
+}  // namespace adasap

@@ -1,0 +1,95 @@
+// Random draws of Alg. 2: the row block B (host, Floyd's algorithm) and Gaussian
+// matrices (device, Box-Muller) from Philox4x64-10 streams (seed, purpose, t).
+//   uniform in (0,1]: ((w >> 11) + 1) 2^-53;  uniform in [0,1): (w >> 11) 2^-53
+//   normal number e: sqrt(-2 ln u1) cos(2 pi u2) with u1 from word 2e, u2 from word 2e+1
+//   bounded integer in [0, s): Lemire's multiply-shift with rejection
+#include <algorithm>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.h"
+
+namespace adasap {
+
+namespace {
+
+// one Philox block gives the four words 4i..4i+3 = normals 2i and 2i+1
+__global__ void normals_kernel(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
+                               double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (2 * i >= count) return;
+  const u64x4 w = philox4x64_10((uint64_t)i + 1, t, 0, 0, seed, purpose);
+  const double two_pi = 6.283185307179586;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t e = 2 * i + h;
+    if (e >= count) break;
+    const double u1 = ((double)(w.v[2 * h] >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(w.v[2 * h + 1] >> 11) * 0x1.0p-53;
+    out[e] = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+  }
+}
+
+struct HostStream {
+  uint64_t seed, purpose, t;
+  uint64_t block = 0;
+  int pos = 4;
+  u64x4 buf{};
+  uint64_t next() {
+    if (pos == 4) {
+      buf = philox4x64_10(block + 1, t, 0, 0, seed, purpose);
+      ++block;
+      pos = 0;
+    }
+    return buf.v[pos++];
+  }
+};
+
+uint64_t bounded(HostStream& hs, uint64_t s) {
+  uint64_t x = hs.next();
+  unsigned __int128 m = (unsigned __int128)x * s;
+  uint64_t low = (uint64_t)m;
+  if (low < s) {
+    const uint64_t threshold = (0 - s) % s;
+    while (low < threshold) {
+      x = hs.next();
+      m = (unsigned __int128)x * s;
+      low = (uint64_t)m;
+    }
+  }
+  return (uint64_t)(m >> 64);
+}
+
+}  // namespace
+
+adasap_status_t normals_dev(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
+                            double* out, hipStream_t s) {
+  if (count <= 0) return ADASAP_OK;
+  const int64_t blocks = (count + 1) / 2;
+  hipLaunchKernelGGL(normals_kernel, dim3((unsigned)((blocks + 255) / 256)), dim3(256), 0, s,
+                     seed, purpose, t, count, out);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+void sample_block_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n, int64_t b,
+                       int64_t* out) {
+  HostStream hs{seed, purpose, t};
+  if (b == n) {
+    for (int64_t i = 0; i < n; ++i) out[i] = i;
+    // draws are still consumed in the oracle's order; the result is all of [0, n)
+    return;
+  }
+  std::unordered_set<int64_t> chosen;
+  chosen.reserve((size_t)b * 2);
+  int64_t cnt = 0;
+  for (int64_t j = n - b; j < n; ++j) {
+    const int64_t v = (int64_t)bounded(hs, (uint64_t)j + 1);
+    const int64_t pick = chosen.count(v) ? j : v;
+    chosen.insert(pick);
+    out[cnt++] = pick;
+  }
+  std::sort(out, out + b);
+}
+
+}  // namespace adasap

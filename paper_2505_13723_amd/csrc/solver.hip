@@ -1,0 +1,758 @@
+// The ADASAP iteration (Alg. 2) on one GPU: handle, workspace, the per-iteration
+// sequence of kernels, residual checks, refinement sweeps, prediction.
+//
+// One iteration t (Sec. 4.2):
+//   Step I    B_t sampled on the host (Floyd), copied to the device;
+//             G = K(X_B, X) Z_t + lambda Z_t[B] - Y_B               (kernel-block product)
+//   Step II   Omega ~ N(0,1)^{b x r} (device Philox), Y_sk = K_BB Omega
+//   Step III  Nystrom: Mo = Omega^T Y_sk, Qo = Omega^T Omega, Cholesky of
+//             sym(Mo) + Delta Qo, B = (Y_sk + Delta Omega) R^{-1}, Jacobi eigenpairs of
+//             B^T B, U = B V Sigma^{-1}, S = max(0, Sigma^2 - Delta), rho;
+//             eta = 1 / Rayleigh quotient of 10 powering steps on P^{-1/2}(K_BB+lambda I)P^{-1/2}
+//   Step IV   D = P^{-1} G (Woodbury), Nesterov update of (V, Z) (W only when needed)
+// All scalars of an iteration stay on the device; the host only launches kernels.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "mfma.h"
+
+namespace adasap {
+
+adasap_status_t colsq(int64_t rows, int k, const void* a, DT t, int64_t lda, double* out,
+                      DevBuf& tmp, hipStream_t s);
+
+adasap_status_t DevBuf::ensure(size_t want) {
+  if (want <= bytes && p) return ADASAP_OK;
+  release();
+  if (want == 0) want = 16;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    p = nullptr;
+    bytes = 0;
+    (void)hipGetLastError();
+    set_error("device allocation of " + std::to_string(want) + " bytes failed");
+    return ADASAP_ERR_OOM;
+  }
+  bytes = want;
+  return ADASAP_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+}  // namespace adasap
+
+using namespace adasap;
+
+struct adasap_handle_s {
+  adasap_config_t cfg;
+  int64_t n = 0;
+  int d = 0, k = 0;
+  DT dtype = DT::F32;  // X, Y, W, predictions
+  DT st = DT::F32;     // iterate state V, Z
+  hipStream_t s = nullptr;
+  const void* X = nullptr;
+  const void* Y = nullptr;
+  double mu = 0, nu = 0;
+  NestCoef nc{};
+  bool use_mfma = false;
+  MfmaPack pack;  // packed coordinates for the matrix-core kernel
+  // workspace
+  DevBuf V, Z, Bdev, XB, G, D, Om, Ysk, Mo, Qo, Rinv, H, evals, Vr, T, S, cinv, cisq, Bm, U, rot;
+  DevBuf vv, ww, uu, zz, coef, part_kb, part_g, part_d, scb, tail, res, rhs, delta_w, tmp, colq;
+  DevBuf zpack;  // float16 copy of Z for the matrix-core kernel
+  int64_t* Bhost[2] = {nullptr, nullptr};
+  hipEvent_t bev[2] = {nullptr, nullptr};
+  IterScalars* sc_host = nullptr;  // pinned trace of per-iteration scalars
+  int64_t sc_host_cap = 0;
+  std::vector<double> eta_tr, rho_tr, lh_tr;
+  ~adasap_handle_s() {
+    for (int i = 0; i < 2; ++i) {
+      if (Bhost[i]) (void)hipHostFree(Bhost[i]);
+      if (bev[i]) (void)hipEventDestroy(bev[i]);
+    }
+    if (sc_host) (void)hipHostFree(sc_host);
+  }
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
+
+adasap_status_t invalid(const std::string& m) {
+  set_error(m);
+  return ADASAP_ERR_INVALID_ARG;
+}
+
+adasap_status_t validate(const adasap_config_t* c, int64_t n, int d, int k) {
+  if (!c) return invalid("config is null");
+  if (c->struct_size != sizeof(adasap_config_t)) return invalid("config struct_size mismatch");
+  if (c->kernel < 0 || c->kernel > 3) return invalid("unknown kernel");
+  if (!finite_pos(c->lengthscale)) return invalid("lengthscale must be finite and > 0");
+  if (!finite_pos(c->lambda)) return invalid("lambda must be finite and > 0");
+  if (n < 1) return invalid("n must be >= 1");
+  if (d < 1 || d > 64) return invalid("d must be in [1, 64]");
+  if (k < 1 || k > 128) return invalid("k must be in [1, 128]");
+  if (c->block_size < 1 || c->block_size > n) return invalid("block size must be in [1, n]");
+  if (c->precond != ADASAP_PRECOND_NYSTROM && c->precond != ADASAP_PRECOND_IDENTITY)
+    return invalid("unknown preconditioner");
+  if (c->precond == ADASAP_PRECOND_NYSTROM &&
+      (c->rank < 1 || c->rank > 128 || c->rank > c->block_size))
+    return invalid("rank must be in [1, min(b, 128)]");
+  if (c->rho_rule != 0 && c->rho_rule != 1) return invalid("rho_rule must be 0 or 1");
+  if (c->rho_rule == 1 && !finite_pos(c->rho)) return invalid("rho must be finite and > 0");
+  if (c->precision < 0 || c->precision > 2) return invalid("unknown precision");
+  if (c->precision == ADASAP_MIXED && d > 16) return invalid("MIXED precision needs d <= 16");
+  if (c->precision == ADASAP_MIXED && c->accel && !c->grad_at_z)
+    return invalid("MIXED precision evaluates the gradient at Z (grad_at_z = 1)");
+  if (c->power_iters < 1 || c->power_iters > 1000) return invalid("power_iters must be in [1, 1000]");
+  if (c->max_iters < 0) return invalid("max_iters must be >= 0");
+  if (!(c->tol >= 0) || !std::isfinite(c->tol)) return invalid("tol must be finite and >= 0");
+  if (c->check_every < 0) return invalid("check_every must be >= 0");
+  if (c->refine_sweeps < 0 || c->refine_sweeps > 16) return invalid("refine_sweeps must be in [0, 16]");
+  const double mu = c->mu > 0 ? c->mu : c->lambda;
+  const double nu = c->nu > 0 ? c->nu : (double)n / (double)c->block_size;
+  if (!std::isfinite(mu) || !std::isfinite(nu)) return invalid("mu and nu must be finite");
+  if (c->accel && mu > nu) return invalid("need mu <= nu (beta >= 0)");
+  return ADASAP_OK;
+}
+
+DT to_dt(int32_t dtype) { return dtype == ADASAP_DTYPE_F64 ? DT::F64 : DT::F32; }
+
+double sketch_eps(int prec) { return prec == ADASAP_FP64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23); }
+
+// K(rows, cols) R with the handle's precision and kernel
+adasap_status_t hk_kblock(adasap_handle_t h, int64_t m, int64_t n, const void* Xr,
+                          const int64_t* ridx, DT xt, const void* Xc, const void* R, DT rt,
+                          int64_t ldr, int kk, void* out, DT ot, int64_t ldo, const KbEpilogue& ep,
+                          bool cols_are_X, int prec) {
+  return kblock_valu(h->cfg.kernel, h->cfg.lengthscale, prec, m, n, h->d, kk, Xr, ridx, xt, Xc, R,
+                     rt, ldr, out, ot, ldo, ep, h->part_kb, h->s);
+  (void)cols_are_X;
+}
+
+// P^{-1} X (power 0) or P^{-1/2} X (power 1) for the current Nystrom factors; X, out b x kk
+adasap_status_t precond_apply_h(adasap_handle_t h, int kk, const double* Xin, double* out,
+                                int power) {
+  const int64_t b = h->cfg.block_size;
+  const int r = h->cfg.rank;
+  IterScalars* sc = h->scb.as<IterScalars>();
+  ADASAP_TRY(gram(b, r, kk, h->U.p, DT::F64, r, Xin, DT::F64, kk, h->coef.as<double>(),
+                  power == 0 ? h->cinv.as<double>() : h->cisq.as<double>(), h->part_g, h->s));
+  return gemm_rm(b, r, kk, h->U.as<double>(), nullptr, nullptr, r, h->coef.as<double>(), out, kk,
+                 Xin, kk, &sc->rho, power == 0 ? 1 : 2, h->s);
+}
+
+// one ADASAP iteration; rhs is the current right-hand side (Y or a refinement residual)
+adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* rhs, DT rhst,
+                        void* Wout) {
+  const adasap_config_t& c = h->cfg;
+  const int64_t n = h->n, b = c.block_size;
+  const int k = h->k, r = c.rank, d = h->d;
+  hipStream_t s = h->s;
+  IterScalars* sc = h->scb.as<IterScalars>();
+  const int prec = c.precision;
+  const int kprec = prec == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
+
+  // Step I: block B_t (host Floyd -> pinned slot -> device)
+  const int slot = (int)(t & 1);
+  ADASAP_HIP(hipEventSynchronize(h->bev[slot]));
+  sample_block_host(c.seed, PURPOSE_B + off, (uint64_t)t, n, b, h->Bhost[slot]);
+  ADASAP_HIP(hipMemcpyAsync(h->Bdev.p, h->Bhost[slot], b * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  ADASAP_HIP(hipEventRecord(h->bev[slot], s));
+  const int64_t* B = h->Bdev.as<int64_t>();
+  ADASAP_TRY(gather_rows(b, d, h->X, h->dtype, d, B, h->XB.p, h->dtype, d, s));
+
+  // gradient block at Z (accelerated; the reading of Alg. 2 Step IV), at W_t (accelerated,
+  // printed form) or at the iterate (plain steps keep the iterate in Z)
+  const bool at_w = c.accel && !c.grad_at_z;
+  const void* gp = at_w ? Wout : h->Z.p;
+  const DT gt = at_w ? h->dtype : h->st;
+  KbEpilogue epg;
+  epg.E1 = gp;
+  epg.e1t = gt;
+  epg.e1idx = B;
+  epg.lde1 = k;
+  epg.a1 = c.lambda;
+  epg.E2 = rhs;
+  epg.e2t = rhst;
+  epg.e2idx = B;
+  epg.lde2 = k;
+  epg.a2 = -1.0;
+  if (h->use_mfma) {
+    ADASAP_TRY(mfma_kblock_rows(h->pack, c.kernel, c.lengthscale, prec, B, b, h->zpack.p, h->Z.p,
+                                h->st, k, h->G.p, epg, h->part_kb, s));
+  } else {
+    ADASAP_TRY(hk_kblock(h, b, n, h->X, B, h->dtype, h->X, gp, gt, k, k, h->G.p, DT::F64, k,
+                         epg, true, kprec));
+  }
+
+  const bool nys = c.precond == ADASAP_PRECOND_NYSTROM;
+  if (nys) {
+    // Step II: sketch
+    ADASAP_TRY(normals_dev(c.seed, PURPOSE_OMEGA + off, (uint64_t)t, b * r, h->Om.as<double>(), s));
+    KbEpilogue none;
+    ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, h->Om.p, DT::F64, r, r,
+                         h->Ysk.p, DT::F64, r, none, false, kprec));
+    // Step III: Nystrom factors
+    ADASAP_TRY(gram(b, r, r, h->Om.p, DT::F64, r, h->Ysk.p, DT::F64, r, h->Mo.as<double>(), nullptr,
+                    h->part_g, s));
+    ADASAP_TRY(gram(b, r, r, h->Om.p, DT::F64, r, h->Om.p, DT::F64, r, h->Qo.as<double>(), nullptr,
+                    h->part_g, s));
+    ADASAP_TRY(nys_core(r, h->Mo.as<double>(), h->Qo.as<double>(), sketch_eps(prec),
+                        h->Rinv.as<double>(), nullptr, sc, s));
+    ADASAP_TRY(gemm_rm(b, r, r, h->Ysk.as<double>(), h->Om.as<double>(), &sc->delta, r,
+                       h->Rinv.as<double>(), h->Bm.as<double>(), r, nullptr, 0, nullptr, 0, s));
+    ADASAP_TRY(gram(b, r, r, h->Bm.p, DT::F64, r, h->Bm.p, DT::F64, r, h->H.as<double>(), nullptr,
+                    h->part_g, s));
+    ADASAP_TRY(jacobi_eig(r, h->H.as<double>(), h->evals.as<double>(), h->Vr.as<double>(),
+                          h->rot.as<double>(), sc, s));
+    ADASAP_TRY(nys_finalize(r, h->evals.as<double>(), h->Vr.as<double>(), c.rho_rule, c.lambda,
+                            c.rho, h->S.as<double>(), h->T.as<double>(), h->cinv.as<double>(),
+                            h->cisq.as<double>(), sc, s));
+    ADASAP_TRY(gemm_rm(b, r, r, h->Bm.as<double>(), nullptr, nullptr, r, h->T.as<double>(),
+                       h->U.as<double>(), r, nullptr, 0, nullptr, 0, s));
+  }
+  // step size by randomized powering
+  double* v = h->vv.as<double>();
+  double* w = h->ww.as<double>();
+  double* u = h->uu.as<double>();
+  double* z = h->zz.as<double>();
+  ADASAP_TRY(normals_dev(c.seed, PURPOSE_POW + off, (uint64_t)t, b, v, s));
+  ADASAP_TRY(normalize_inplace(b, v, sc, h->part_d, s));
+  for (int i = 0; i < c.power_iters; ++i) {
+    const double* win = v;
+    if (nys) {
+      ADASAP_TRY(precond_apply_h(h, 1, v, w, 1));
+      win = w;
+    }
+    KbEpilogue epp;
+    epp.E1 = win;
+    epp.e1t = DT::F64;
+    epp.lde1 = 1;
+    epp.a1 = c.lambda;
+    ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, win, DT::F64, 1, 1, u,
+                         DT::F64, 1, epp, false, kprec));
+    const double* zin = u;
+    if (nys) {
+      ADASAP_TRY(precond_apply_h(h, 1, u, z, 1));
+      zin = z;
+    }
+    ADASAP_TRY(dots_vz(b, v, zin, sc, h->part_d, s));
+    ADASAP_TRY(normalize_into(b, zin, v, sc, i == c.power_iters - 1 ? 1 : 0, s));
+  }
+  // Step IV: direction and update
+  const double* Dp = h->G.as<double>();
+  if (nys) {
+    ADASAP_TRY(precond_apply_h(h, k, h->G.as<double>(), h->D.as<double>(), 0));
+    Dp = h->D.as<double>();
+  }
+  if (c.accel) ADASAP_TRY(nesterov_dense(n * k, h->V.p, h->Z.p, h->st, h->nc, Wout, h->dtype, s));
+  ADASAP_TRY(nesterov_sparse(b, k, B, Dp, h->V.p, h->Z.p, h->st, h->nc, sc, c.accel ? Wout : nullptr,
+                             h->dtype, s));
+  if (h->use_mfma) ADASAP_TRY(mfma_pack_rhs(h->pack, h->Z.p, h->st, k, h->zpack.p, s));
+  return ADASAP_OK;
+}
+
+adasap_status_t residual_h(adasap_handle_t h, const void* W, DT wt, const void* rhs, DT rhst,
+                           double* relres, double* relmax, bool keep) {
+  const int64_t n = h->n;
+  const int k = h->k;
+  ADASAP_TRY(h->res.ensure((size_t)n * k * sizeof(double)));
+  ADASAP_TRY(h->colq.ensure(2 * (size_t)k * sizeof(double)));
+  KbEpilogue ep;
+  ep.E1 = W;
+  ep.e1t = wt;
+  ep.lde1 = k;
+  ep.a1 = h->cfg.lambda;
+  ep.E2 = rhs;
+  ep.e2t = rhst;
+  ep.lde2 = k;
+  ep.a2 = -1.0;
+  if (h->use_mfma) {
+    ADASAP_TRY(mfma_residual(h->pack, h->cfg.kernel, h->cfg.lengthscale, W, wt, k, h->res.p, ep,
+                             h->part_kb, h->tmp, h->s));
+  } else {
+    ADASAP_TRY(hk_kblock(h, n, n, h->X, nullptr, h->dtype, h->X, W, wt, k, k, h->res.p, DT::F64, k,
+                         ep, true, ADASAP_FP64));
+  }
+  double* cq = h->colq.as<double>();
+  ADASAP_TRY(colsq(n, k, h->res.p, DT::F64, k, cq, h->tmp, h->s));
+  ADASAP_TRY(colsq(n, k, rhs, rhst, k, cq + k, h->tmp, h->s));
+  std::vector<double> hq(2 * (size_t)k);
+  ADASAP_HIP(hipMemcpyAsync(hq.data(), cq, 2 * (size_t)k * sizeof(double), hipMemcpyDeviceToHost, h->s));
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  double rs = 0, ys = 0, mx = 0;
+  for (int c = 0; c < k; ++c) {
+    rs += hq[c];
+    ys += hq[k + c];
+    const double col = hq[k + c] > 0 ? std::sqrt(hq[c] / hq[k + c]) : std::sqrt(hq[c]);
+    mx = col > mx ? col : mx;
+  }
+  if (relres) *relres = ys > 0 ? std::sqrt(rs / ys) : std::sqrt(rs);
+  if (relmax) *relmax = mx;
+  (void)keep;
+  return ADASAP_OK;
+}
+
+// solve (K + lambda I) Wst = rhs from the state already in (V, Z); writes W (handle dtype)
+adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT rhst, void* W,
+                          int64_t& iters_done, double& relres, double& relmax, double& solve_ms,
+                          double& check_ms, int64_t& trace_pos) {
+  const adasap_config_t& c = h->cfg;
+  const int64_t nk = h->n * h->k;
+  hipEvent_t e0, e1;
+  ADASAP_HIP(hipEventCreate(&e0));
+  ADASAP_HIP(hipEventCreate(&e1));
+  const bool tail = c.tail_average != 0;
+  int64_t tail_count = 0;
+  if (tail) {
+    ADASAP_TRY(h->tail.ensure((size_t)nk * sizeof(double)));
+    ADASAP_HIP(hipMemsetAsync(h->tail.p, 0, (size_t)nk * sizeof(double), h->s));
+  }
+  const int64_t T = c.max_iters;
+  const int64_t every = (c.tol > 0) ? (c.check_every > 0 ? c.check_every : T) : 0;
+  for (int64_t t = 0; t < T; ++t) {
+    if (tail && t >= T / 2) {
+      ADASAP_TRY(accumulate(nk, W, h->dtype, h->tail.as<double>(), h->s));
+      ++tail_count;
+    }
+    const bool check_now = every > 0 && ((t + 1) % every == 0 || t + 1 == T);
+    const bool need_w = tail || check_now || t + 1 == T || (c.accel && !c.grad_at_z);
+    ADASAP_HIP(hipEventRecord(e0, h->s));
+    ADASAP_TRY(iterate(h, t, off, rhs, rhst, need_w || !c.accel ? W : nullptr));
+    ADASAP_HIP(hipEventRecord(e1, h->s));
+    if (trace_pos < h->sc_host_cap) {
+      ADASAP_HIP(hipMemcpyAsync(h->sc_host + trace_pos, h->scb.p, sizeof(IterScalars),
+                                hipMemcpyDeviceToHost, h->s));
+    }
+    ++trace_pos;
+    ++iters_done;
+    ADASAP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    ADASAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    solve_ms += ms;
+    if (!c.accel && need_w) ADASAP_TRY(convert(nk, h->Z.p, h->st, W, h->dtype, h->s));
+    if (check_now) {
+      auto c0 = std::chrono::steady_clock::now();
+      ADASAP_TRY(residual_h(h, W, h->dtype, rhs, rhst, &relres, &relmax, false));
+      check_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+      if (!std::isfinite(relres)) {
+        set_error("non-finite residual");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return ADASAP_ERR_NONFINITE;
+      }
+      if (relres <= c.tol) break;
+    }
+  }
+  if (!c.accel) ADASAP_TRY(convert(nk, h->Z.p, h->st, W, h->dtype, h->s));
+  if (tail && tail_count > 0)
+    ADASAP_TRY(scale_store(nk, h->tail.as<double>(), 1.0 / (double)tail_count, W, h->dtype, h->s));
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ADASAP_OK;
+}
+
+}  // namespace
+
+namespace adasap {
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace adasap
+
+extern "C" {
+
+adasap_status_t adasap_config_default(adasap_config_t* cfg) {
+  if (!cfg) return invalid("config is null");
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->struct_size = sizeof(adasap_config_t);
+  cfg->kernel = ADASAP_RBF;
+  cfg->lengthscale = 1.0;
+  cfg->lambda = 1e-2;
+  cfg->block_size = 256;
+  cfg->rank = 64;
+  cfg->rho_rule = 0;
+  cfg->rho = 0.0;
+  cfg->mu = 0.0;
+  cfg->nu = 0.0;
+  cfg->power_iters = 10;
+  cfg->max_iters = 100;
+  cfg->tol = 0.0;
+  cfg->check_every = 0;
+  cfg->refine_sweeps = 0;
+  cfg->precond = ADASAP_PRECOND_NYSTROM;
+  cfg->precision = ADASAP_FP32;
+  cfg->seed = 0;
+  cfg->accel = 1;
+  cfg->grad_at_z = 1;
+  cfg->z_uses_v_next = 1;
+  cfg->tail_average = 0;
+  return ADASAP_OK;
+}
+
+int64_t adasap_workspace_bytes(const adasap_config_t* cfg, int64_t n, int32_t d, int32_t k) {
+  if (validate(cfg, n, d, k) != ADASAP_OK) return 0;
+  const int64_t b = cfg->block_size, r = cfg->rank;
+  const int64_t st = cfg->precision == ADASAP_FP64 ? 8 : 4;
+  int64_t bytes = 2 * n * k * st;                       // V, Z
+  bytes += b * (8 + 8 * d + 16 * k + 24 * r + 32);      // B, X_B, G, D, Omega, Y_sk, B, U, vectors
+  bytes += 8 * r * r * 8 + 8 * (int64_t)jacobi_rot_capacity((int)r);
+  if (cfg->precision == ADASAP_MIXED) bytes += mfma_pack_bytes(n, d, k);
+  return bytes;
+}
+
+adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, int32_t k,
+                              const void* X, const void* Y, int32_t dtype, void* stream,
+                              adasap_handle_t* out) {
+  if (!out) return invalid("out handle pointer is null");
+  *out = nullptr;
+  ADASAP_TRY(validate(cfg, n, d, k));
+  if (!X || !Y) return invalid("X and Y must be non-null device pointers");
+  if (dtype != ADASAP_DTYPE_F32 && dtype != ADASAP_DTYPE_F64) return invalid("unknown dtype");
+  auto* h = new (std::nothrow) adasap_handle_s();
+  if (!h) return ADASAP_ERR_OOM;
+  h->cfg = *cfg;
+  h->n = n;
+  h->d = d;
+  h->k = k;
+  h->dtype = to_dt(dtype);
+  h->st = cfg->precision == ADASAP_FP64 ? DT::F64 : DT::F32;
+  h->s = static_cast<hipStream_t>(stream);
+  h->X = X;
+  h->Y = Y;
+  h->mu = cfg->mu > 0 ? cfg->mu : cfg->lambda;
+  h->nu = cfg->nu > 0 ? cfg->nu : (double)n / (double)cfg->block_size;
+  h->nc.beta = 1.0 - std::sqrt(h->mu / h->nu);
+  h->nc.gamma = 1.0 / std::sqrt(h->mu * h->nu);
+  h->nc.alpha = 1.0 / (1.0 + h->nc.gamma * h->nu);
+  h->nc.accel = cfg->accel ? 1 : 0;
+  h->nc.z_uses_v_next = cfg->z_uses_v_next ? 1 : 0;
+  h->use_mfma = cfg->precision == ADASAP_MIXED;
+  auto fail = [&](adasap_status_t st) {
+    delete h;
+    return st;
+  };
+  const int64_t b = cfg->block_size;
+  const int r = cfg->rank > 0 ? cfg->rank : 1;
+  const size_t ss = dt_size(h->st);
+  adasap_status_t st = ADASAP_OK;
+#define ENS(buf, bytes) \
+  if ((st = h->buf.ensure((size_t)(bytes))) != ADASAP_OK) return fail(st)
+  ENS(V, n * k * ss);
+  ENS(Z, n * k * ss);
+  ENS(Bdev, b * 8);
+  ENS(XB, b * d * dt_size(h->dtype));
+  ENS(G, b * k * 8);
+  ENS(D, b * k * 8);
+  ENS(Om, b * r * 8);
+  ENS(Ysk, b * r * 8);
+  ENS(Bm, b * r * 8);
+  ENS(U, b * r * 8);
+  ENS(Mo, r * r * 8);
+  ENS(Qo, r * r * 8);
+  ENS(Rinv, r * r * 8);
+  ENS(H, r * r * 8);
+  ENS(Vr, r * r * 8);
+  ENS(T, r * r * 8);
+  ENS(evals, r * 8);
+  ENS(S, r * 8);
+  ENS(cinv, r * 8);
+  ENS(cisq, r * 8);
+  ENS(coef, (size_t)r * (k > 1 ? k : 1) * 8);
+  ENS(rot, jacobi_rot_capacity(r) * 8);
+  ENS(vv, b * 8);
+  ENS(ww, b * 8);
+  ENS(uu, b * 8);
+  ENS(zz, b * 8);
+  ENS(scb, sizeof(IterScalars));
+#undef ENS
+  if (hipHostMalloc((void**)&h->Bhost[0], b * sizeof(int64_t)) != hipSuccess ||
+      hipHostMalloc((void**)&h->Bhost[1], b * sizeof(int64_t)) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    return fail(ADASAP_ERR_OOM);
+  }
+  if (hipEventCreateWithFlags(&h->bev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->bev[1], hipEventDisableTiming) != hipSuccess) {
+    set_error("event creation failed");
+    return fail(ADASAP_ERR_DEVICE);
+  }
+  if (hipMemsetAsync(h->scb.p, 0, sizeof(IterScalars), h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
+  if (h->use_mfma) {
+    if ((st = mfma_pack_create(h->pack, n, d, k, X, h->dtype, cfg->kernel, cfg->lengthscale, h->s)) != ADASAP_OK)
+      return fail(st);
+    if ((st = h->zpack.ensure(mfma_rhs_bytes(h->pack, k))) != ADASAP_OK) return fail(st);
+  }
+  if (hipStreamSynchronize(h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
+  *out = h;
+  return ADASAP_OK;
+}
+
+adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report) {
+  if (!h) return invalid("handle is null");
+  if (!W) return invalid("W must be a non-null device pointer");
+  const adasap_config_t& c = h->cfg;
+  const int64_t nk = h->n * h->k;
+  adasap_report_t rep;
+  std::memset(&rep, 0, sizeof(rep));
+  rep.relres = -1;
+  rep.relres_maxcol = -1;
+  int nf = 0;
+  ADASAP_TRY(any_nonfinite(h->n * h->d, h->X, h->dtype, &nf, h->tmp, h->s));
+  if (!nf) ADASAP_TRY(any_nonfinite(nk, h->Y, h->dtype, &nf, h->tmp, h->s));
+  if (!nf) ADASAP_TRY(any_nonfinite(nk, W, h->dtype, &nf, h->tmp, h->s));
+  if (nf) {
+    set_error("X, Y or W0 contains NaN or Inf");
+    return ADASAP_ERR_NONFINITE;
+  }
+  const int64_t total_iters = c.max_iters * (1 + c.refine_sweeps);
+  if (h->sc_host_cap < total_iters) {
+    if (h->sc_host) (void)hipHostFree(h->sc_host);
+    h->sc_host = nullptr;
+    h->sc_host_cap = 0;
+    if (total_iters > 0) {
+      if (hipHostMalloc((void**)&h->sc_host, total_iters * sizeof(IterScalars)) != hipSuccess) {
+        set_error("pinned host allocation failed");
+        return ADASAP_ERR_OOM;
+      }
+      h->sc_host_cap = total_iters;
+    }
+  }
+  // V_0 = Z_0 = W_0
+  ADASAP_TRY(convert(nk, W, h->dtype, h->V.p, h->st, h->s));
+  ADASAP_TRY(convert(nk, W, h->dtype, h->Z.p, h->st, h->s));
+  if (h->use_mfma) ADASAP_TRY(mfma_pack_rhs(h->pack, h->Z.p, h->st, h->k, h->zpack.p, h->s));
+  int64_t trace_pos = 0;
+  double relres = -1, relmax = -1;
+  ADASAP_TRY(run_sweep(h, 0, h->Y, h->dtype, W, rep.iters, relres, relmax, rep.solve_ms,
+                       rep.check_ms, trace_pos));
+  // float64 iterative refinement: R = Y - (K + lambda I) W, solve for the correction, add it
+  for (int sw = 1; sw <= c.refine_sweeps; ++sw) {
+    ADASAP_TRY(h->rhs.ensure((size_t)nk * sizeof(double)));
+    ADASAP_TRY(h->delta_w.ensure((size_t)nk * dt_size(h->dtype)));
+    double rr = 0;
+    ADASAP_TRY(residual_h(h, W, h->dtype, h->Y, h->dtype, &rr, nullptr, false));
+    // rhs = -(K W + lambda W - Y)
+    ADASAP_TRY(scale_store(nk, h->res.as<double>(), -1.0, h->rhs.p, DT::F64, h->s));
+    ADASAP_HIP(hipMemsetAsync(h->delta_w.p, 0, (size_t)nk * dt_size(h->dtype), h->s));
+    ADASAP_HIP(hipMemsetAsync(h->V.p, 0, (size_t)nk * dt_size(h->st), h->s));
+    ADASAP_HIP(hipMemsetAsync(h->Z.p, 0, (size_t)nk * dt_size(h->st), h->s));
+    if (h->use_mfma) ADASAP_TRY(mfma_pack_rhs(h->pack, h->Z.p, h->st, h->k, h->zpack.p, h->s));
+    double r2 = -1, m2 = -1;
+    ADASAP_TRY(run_sweep(h, PURPOSE_SWEEP_STRIDE * (uint64_t)sw, h->rhs.p, DT::F64, h->delta_w.p,
+                         rep.iters, r2, m2, rep.solve_ms, rep.check_ms, trace_pos));
+    ADASAP_TRY(add_inplace(nk, W, h->dtype, h->delta_w.p, h->dtype, h->s));
+    rep.refine_done = sw;
+    relres = -1;
+  }
+  if (c.refine_sweeps > 0 && c.tol > 0) {
+    auto c0 = std::chrono::steady_clock::now();
+    ADASAP_TRY(residual_h(h, W, h->dtype, h->Y, h->dtype, &relres, &relmax, false));
+    rep.check_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+  }
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  const int64_t ntr = trace_pos < h->sc_host_cap ? trace_pos : h->sc_host_cap;
+  h->eta_tr.resize(ntr);
+  h->rho_tr.resize(ntr);
+  h->lh_tr.resize(ntr);
+  for (int64_t i = 0; i < ntr; ++i) {
+    h->eta_tr[i] = h->sc_host[i].eta;
+    h->rho_tr[i] = h->sc_host[i].rho;
+    h->lh_tr[i] = h->sc_host[i].lam_hat;
+    rep.not_pd_events += h->sc_host[i].not_pd;
+    if (h->sc_host[i].failed) {
+      set_error("Nystrom core not positive definite after shift retries");
+      rep.status = ADASAP_ERR_NOT_PD;
+    }
+  }
+  if (ntr > 0) {
+    rep.eta_last = h->eta_tr[ntr - 1];
+    rep.rho_last = h->rho_tr[ntr - 1];
+    rep.lambda_hat_last = h->lh_tr[ntr - 1];
+    rep.delta_last = h->sc_host[ntr - 1].delta;
+  }
+  rep.relres = relres;
+  rep.relres_maxcol = relmax;
+  if (report) *report = rep;
+  return rep.status == ADASAP_OK ? ADASAP_OK : (adasap_status_t)rep.status;
+}
+
+adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, const void* Xstar,
+                               void* out) {
+  if (!h) return invalid("handle is null");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return ADASAP_OK;
+  if (!W || !Xstar || !out) return invalid("W, Xstar and out must be non-null device pointers");
+  KbEpilogue none;
+  const int kprec = h->cfg.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
+  ADASAP_TRY(hk_kblock(h, m, h->n, Xstar, nullptr, h->dtype, h->X, W, h->dtype, h->k, h->k, out,
+                       h->dtype, h->k, none, true, kprec));
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  return ADASAP_OK;
+}
+
+adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres,
+                                double* relres_maxcol) {
+  if (!h) return invalid("handle is null");
+  if (!W) return invalid("W must be a non-null device pointer");
+  return residual_h(h, W, h->dtype, h->Y, h->dtype, relres, relres_maxcol, false);
+}
+
+adasap_status_t adasap_get_trace(adasap_handle_t h, double* eta, double* rho, double* lambda_hat,
+                                 int64_t count) {
+  if (!h) return invalid("handle is null");
+  if (count < 0) return invalid("count must be >= 0");
+  const int64_t m = count < (int64_t)h->eta_tr.size() ? count : (int64_t)h->eta_tr.size();
+  for (int64_t i = 0; i < m; ++i) {
+    if (eta) eta[i] = h->eta_tr[i];
+    if (rho) rho[i] = h->rho_tr[i];
+    if (lambda_hat) lambda_hat[i] = h->lh_tr[i];
+  }
+  return ADASAP_OK;
+}
+
+void adasap_destroy(adasap_handle_t h) {
+  if (!h) return;
+  if (h->s) (void)hipStreamSynchronize(h->s);
+  delete h;
+}
+
+adasap_status_t adasap_sample_block(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n,
+                                    int64_t b, int64_t* out) {
+  if (!out) return invalid("out is null");
+  if (n < 1 || b < 1 || b > n) return invalid("need 1 <= b <= n");
+  sample_block_host(seed, purpose, t, n, b, out);
+  return ADASAP_OK;
+}
+
+adasap_status_t adasap_normals(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
+                               double* out, void* stream) {
+  if (count < 0) return invalid("count must be >= 0");
+  if (count > 0 && !out) return invalid("out is null");
+  ADASAP_TRY(normals_dev(seed, purpose, t, count, out, static_cast<hipStream_t>(stream)));
+  ADASAP_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  return ADASAP_OK;
+}
+
+adasap_status_t adasap_kblock_matmul(int32_t kernel, double lengthscale, int32_t precision,
+                                     int64_t m, int64_t n, int32_t d, int32_t k, const void* Xr,
+                                     const void* Xc, const void* R, void* out, int32_t dtype,
+                                     void* stream) {
+  if (kernel < 0 || kernel > 3) return invalid("unknown kernel");
+  if (!finite_pos(lengthscale)) return invalid("lengthscale must be finite and > 0");
+  if (precision < 0 || precision > 2) return invalid("unknown precision");
+  if (m < 0 || n < 0) return invalid("m and n must be >= 0");
+  if (d < 1 || d > 64) return invalid("d must be in [1, 64]");
+  if (k < 1 || k > 128) return invalid("k must be in [1, 128]");
+  if (precision == ADASAP_MIXED && d > 16) return invalid("MIXED precision needs d <= 16");
+  if (dtype != ADASAP_DTYPE_F32 && dtype != ADASAP_DTYPE_F64) return invalid("unknown dtype");
+  if (m == 0) return ADASAP_OK;
+  if (!Xr || !out || (n > 0 && (!Xc || !R))) return invalid("null device pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf part;
+  KbEpilogue none;
+  const DT t = to_dt(dtype);
+  if (precision == ADASAP_MIXED && n > 0) {
+    MfmaPack pk;
+    ADASAP_TRY(mfma_pack_create(pk, n, d, k, Xc, t, kernel, lengthscale, s));
+    DevBuf zp;
+    ADASAP_TRY(zp.ensure(mfma_rhs_bytes(pk, k)));
+    ADASAP_TRY(mfma_pack_rhs(pk, R, t, k, zp.p, s));
+    ADASAP_TRY(mfma_kblock_points(pk, kernel, lengthscale, Xr, t, m, zp.p, k, out, t, part, s));
+    ADASAP_HIP(hipStreamSynchronize(s));
+    return ADASAP_OK;
+  }
+  ADASAP_TRY(kblock_valu(kernel, lengthscale, precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32,
+                         m, n, d, k, Xr, nullptr, t, Xc, R, t, k, out, t, k, none, part, s));
+  ADASAP_HIP(hipStreamSynchronize(s));
+  return ADASAP_OK;
+}
+
+adasap_status_t adasap_nystrom(int64_t b, int32_t r, const double* Ysk, const double* Omega,
+                               double eps, double* U, double* S, double* delta, void* stream) {
+  if (b < 1 || r < 1 || r > 128 || r > b) return invalid("need 1 <= r <= min(b, 128)");
+  if (!Ysk || !Omega || !U || !S) return invalid("null device pointer");
+  if (!(eps >= 0) || !std::isfinite(eps)) return invalid("eps must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf Mo, Qo, Rinv, Bm, H, ev, Vr, T, ci, cq, rot, scb, part;
+  ADASAP_TRY(Mo.ensure(r * r * 8));
+  ADASAP_TRY(Qo.ensure(r * r * 8));
+  ADASAP_TRY(Rinv.ensure(r * r * 8));
+  ADASAP_TRY(Bm.ensure(b * r * 8));
+  ADASAP_TRY(H.ensure(r * r * 8));
+  ADASAP_TRY(ev.ensure(r * 8));
+  ADASAP_TRY(Vr.ensure(r * r * 8));
+  ADASAP_TRY(T.ensure(r * r * 8));
+  ADASAP_TRY(ci.ensure(r * 8));
+  ADASAP_TRY(cq.ensure(r * 8));
+  ADASAP_TRY(rot.ensure(jacobi_rot_capacity(r) * 8));
+  ADASAP_TRY(scb.ensure(sizeof(IterScalars)));
+  ADASAP_HIP(hipMemsetAsync(scb.p, 0, sizeof(IterScalars), s));
+  IterScalars* sc = scb.as<IterScalars>();
+  ADASAP_TRY(gram(b, r, r, Omega, DT::F64, r, Ysk, DT::F64, r, Mo.as<double>(), nullptr, part, s));
+  ADASAP_TRY(gram(b, r, r, Omega, DT::F64, r, Omega, DT::F64, r, Qo.as<double>(), nullptr, part, s));
+  ADASAP_TRY(nys_core(r, Mo.as<double>(), Qo.as<double>(), eps, Rinv.as<double>(), nullptr, sc, s));
+  ADASAP_TRY(gemm_rm(b, r, r, Ysk, Omega, &sc->delta, r, Rinv.as<double>(), Bm.as<double>(), r,
+                     nullptr, 0, nullptr, 0, s));
+  ADASAP_TRY(gram(b, r, r, Bm.p, DT::F64, r, Bm.p, DT::F64, r, H.as<double>(), nullptr, part, s));
+  ADASAP_TRY(jacobi_eig(r, H.as<double>(), ev.as<double>(), Vr.as<double>(), rot.as<double>(), sc, s));
+  ADASAP_TRY(nys_finalize(r, ev.as<double>(), Vr.as<double>(), 1, 0.0, 1.0, S, T.as<double>(),
+                          ci.as<double>(), cq.as<double>(), sc, s));
+  ADASAP_TRY(gemm_rm(b, r, r, Bm.as<double>(), nullptr, nullptr, r, T.as<double>(), U, r, nullptr,
+                     0, nullptr, 0, s));
+  IterScalars hs;
+  ADASAP_HIP(hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+  ADASAP_HIP(hipStreamSynchronize(s));
+  if (delta) ADASAP_HIP(hipMemcpy(delta, &hs.delta, sizeof(double), hipMemcpyHostToDevice));
+  if (hs.failed) {
+    set_error("Nystrom core not positive definite after shift retries");
+    return ADASAP_ERR_NOT_PD;
+  }
+  return ADASAP_OK;
+}
+
+adasap_status_t adasap_precond_apply(int64_t b, int32_t r, int32_t k, const double* U,
+                                     const double* S, double rho, int32_t power, const double* G,
+                                     double* out, void* stream) {
+  if (b < 1 || r < 1 || r > 128 || r > b || k < 1 || k > 128) return invalid("bad sizes");
+  if (!finite_pos(rho)) return invalid("rho must be finite and > 0");
+  if (power != 0 && power != 1) return invalid("power must be 0 or 1");
+  if (!U || !S || !G || !out) return invalid("null device pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf coefs, coef, scb, part;
+  ADASAP_TRY(coefs.ensure(r * 8));
+  ADASAP_TRY(coef.ensure((size_t)r * k * 8));
+  ADASAP_TRY(scb.ensure(sizeof(IterScalars)));
+  ADASAP_TRY(woodbury_coefs(r, S, rho, power, coefs.as<double>(), scb.as<IterScalars>(), s));
+  IterScalars* sc = scb.as<IterScalars>();
+  ADASAP_TRY(gram(b, r, k, U, DT::F64, r, G, DT::F64, k, coef.as<double>(), coefs.as<double>(), part, s));
+  ADASAP_TRY(gemm_rm(b, r, k, U, nullptr, nullptr, r, coef.as<double>(), out, k, G, k, &sc->rho,
+                     power == 0 ? 1 : 2, s));
+  ADASAP_HIP(hipStreamSynchronize(s));
+  return ADASAP_OK;
+}
+
+const char* adasap_last_error(void) { return g_last_error.c_str(); }
+
+const char* adasap_status_string(adasap_status_t s) {
+  switch (s) {
+    case ADASAP_OK: return "ok";
+    case ADASAP_ERR_INVALID_ARG: return "invalid argument";
+    case ADASAP_ERR_OOM: return "out of memory";
+    case ADASAP_ERR_DEVICE: return "device error";
+    case ADASAP_ERR_NOT_PD: return "Nystrom core not positive definite";
+    case ADASAP_ERR_NONFINITE: return "non-finite values";
+    case ADASAP_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

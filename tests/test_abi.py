@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol,
+validates arguments before any device work, and its host block sampler draws exactly
+the oracle's blocks (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import rng as orng
+from paper_2505_13723_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hlib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libadasap.so not built")
+    return binding.Library()
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "adasap.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(adasap_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(hlib):
+    names = _declared_functions()
+    assert "adasap_create" in names and "adasap_solve" in names and "adasap_predict" in names
+    for name in names:
+        assert hasattr(hlib.cdll, name), name
+    assert set(names) == set(binding.EXPORTED)
+
+
+def test_config_layout_and_defaults(hlib):
+    cfg = hlib.config()
+    assert cfg.struct_size == ctypes.sizeof(binding.Config)
+    assert cfg.power_iters == 10 and cfg.accel == 1 and cfg.rho_rule == 0 and cfg.grad_at_z == 1
+
+
+def test_status_strings(hlib):
+    for code in range(7):
+        assert hlib.cdll.adasap_status_string(code).decode()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("lam", 0.0), ("lam", -1.0), ("lengthscale", 0.0), ("block_size", 0), ("block_size", 1001),
+    ("rank", 0), ("rank", 129), ("rho_rule", 1), ("kernel", 9), ("precision", 7),
+    ("power_iters", 0), ("mu", 1e6), ("refine_sweeps", 99), ("tol", -1.0), ("precond", 5),
+])
+def test_create_rejects_bad_config_before_device_work(hlib, field, value):
+    kw = dict(block_size=100, rank=20)
+    kw[field] = value
+    cfg = hlib.config(**kw)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    st = hlib.cdll.adasap_create(ctypes.byref(cfg), 1000, 4, 1, fake, fake, 0, None, ctypes.byref(h))
+    assert st == 1, hlib.last_error()
+    assert not h.value
+    assert hlib.last_error()
+
+
+def test_create_rejects_bad_shapes(hlib):
+    cfg = hlib.config(block_size=10, rank=5)
+    fake = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    for n, d, k in [(0, 3, 1), (100, 0, 1), (100, 65, 1), (100, 3, 0), (100, 3, 129)]:
+        assert hlib.cdll.adasap_create(ctypes.byref(cfg), n, d, k, fake, fake, 0, None,
+                                       ctypes.byref(h)) == 1
+    assert hlib.cdll.adasap_create(ctypes.byref(cfg), 100, 3, 1, None, fake, 0, None,
+                                   ctypes.byref(h)) == 1
+    mixed = hlib.config(block_size=10, rank=5, precision=binding.MIXED)
+    assert hlib.cdll.adasap_create(ctypes.byref(mixed), 100, 17, 1, fake, fake, 0, None,
+                                   ctypes.byref(h)) == 1
+
+
+def test_workspace_bytes(hlib):
+    cfg = hlib.config(block_size=256, rank=64)
+    small = hlib.workspace_bytes(cfg, 4096, 8, 1)
+    big = hlib.workspace_bytes(cfg, 8192, 8, 1)
+    assert 0 < small < big
+    bad = hlib.config(block_size=0)
+    assert hlib.workspace_bytes(bad, 4096, 8, 1) == 0
+
+
+@pytest.mark.parametrize("n,b,t,seed", [(4096, 256, 0, 1), (4096, 256, 199, 1), (1000, 999, 3, 7),
+                                        (50, 50, 0, 2), (2_000_000, 300, 5, 3)])
+def test_host_block_sampler_matches_oracle(hlib, n, b, t, seed):
+    mine = hlib.sample_block(seed, binding.PURPOSE_B, t, n, b)
+    ref = orng.sample_block(seed, t, n, b)
+    assert np.array_equal(mine, ref)
+
+
+def test_sample_block_rejects(hlib):
+    out = np.zeros(4, dtype=np.int64)
+    p = out.ctypes.data_as(ctypes.c_void_p)
+    assert hlib.cdll.adasap_sample_block(1, 5, 0, 3, 4, p) == 1
+    assert hlib.cdll.adasap_sample_block(1, 5, 0, 3, 0, p) == 1
