@@ -1,0 +1,163 @@
+"""ADASAP hot-path benchmark on one MI355X (gfx950).
+
+Workload: the 2M-point, 11-dimensional RBF problem with 64 right-hand sides
+(standardised y plus 63 pathwise right-hand sides f_s(X) + eps_s), lambda = 1e-2,
+b = 16384, r = 128, matrix-core float16 kernel-block products with float32
+accumulation (MIXED precision), synthetic seeded data.
+
+A step is one ADASAP iteration (Alg. 2: block sampling, the kernel-block
+gradient, the Nystrom sketch and factorisation, powering, the Woodbury direction
+and the Nesterov update).  `value` is the step-I kernel-block throughput over the
+whole step, pairs * (2d + 2k) flops / step time.  The line also reports the
+time to relative residual 1e-3 (iterations timed on the device, residual checks
+once per data pass off the clock), the roofline of the dominant kernel, and the
+CPU float64 oracle timed on a bounded sample on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-ttr] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time to rel. residual 1e-3 (s) & kernel-block GFLOP/s, n=2M d=11, 1 GPU"
+# published MI355X peaks used for the roofline fraction
+PEAK_F16_MFMA_TFLOPS = 2500.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual run")
+    ap.add_argument("--ttr-passes", type=int, default=40, help="data passes allowed for time-to-residual")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=384)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2505_13723_amd import binding, inputs
+
+    cfgw = dict(inputs.WORKLOADS["c3_rbf_n2m_k64"])
+    n, d, k = args.n, cfgw["d"], cfgw["k"]
+    b, r, lam, ell = cfgw["b"], cfgw["r"], cfgw["lam"], cfgw["ell"]
+    if n != 2_000_000:
+        b = max(256, n // 122)
+    lib = binding.load()
+    log("generating inputs n=%d d=%d k=%d on the GPU" % (n, d, k))
+    X, Y = inputs.make_c3(seed=cfgw["seed"], n=n, d=d, k=k, ell=ell, lam=lam, device="cuda")
+    torch.cuda.synchronize()
+
+    def make(max_iters, tol=0.0, check_every=0, refine=0):
+        c = lib.config(kernel="rbf", lengthscale=ell, lam=lam, block_size=b, rank=r,
+                       max_iters=max_iters, tol=tol, check_every=check_every,
+                       refine_sweeps=refine, seed=cfgw["seed"], precision="mixed")
+        return lib.create(c, X, Y)
+
+    # ---- throughput: warmup, then exactly `steps` timed iterations -------------------------
+    h = make(args.warmup)
+    W = torch.zeros_like(Y)
+    if args.warmup > 0:
+        h.solve(W)
+    h.close()
+    h = make(args.steps)
+    W.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = h.solve(W)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h.close()
+    ms_per_step = rep["solve_ms"] / max(1, rep["iters"])
+    pairs = float(b) * n
+    flops_step1 = pairs * (2 * d + 2 * k)
+    value = flops_step1 / (ms_per_step * 1e-3) / 1e9
+    kern_ms = rep["step1_kernel_ms"] / max(1, rep["step1_launches"])
+    achieved = flops_step1 / (kern_ms * 1e-3) / 1e12
+    log("steps=%d solve_ms=%.1f (%.3f ms/step), wall %.3f s, step-I kernel %.3f ms, "
+        "Jacobi sweeps <= %d" % (rep["iters"], rep["solve_ms"], ms_per_step, wall, kern_ms,
+                                 rep["jacobi_sweeps_max"]))
+
+    # ---- time to relative residual 1e-3 -------------------------------------------------------
+    ttr = None
+    if not args.no_ttr:
+        per_pass = int(math.ceil(n / b))
+        h = make(per_pass * args.ttr_passes, tol=1e-3, check_every=per_pass)
+        W.zero_()
+        rep2 = h.solve(W)
+        h.close()
+        reached = rep2["relres"] >= 0 and rep2["relres"] <= 1e-3
+        ttr = {"seconds": rep2["solve_ms"] / 1e3 if reached else None,
+               "reached": bool(reached), "iterations": rep2["iters"],
+               "passes": rep2["iters"] / per_pass, "relres": rep2["relres"],
+               "relres_maxcol": rep2["relres_maxcol"], "check_every_iters": per_pass,
+               "check_seconds_off_clock": rep2["check_ms"] / 1e3}
+        log("time-to-residual: %s" % json.dumps(ttr))
+
+    # ---- CPU float64 oracle on a bounded sample ------------------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(X, Y, args.cpu_rows, ell, d, k, b, n)
+        log("cpu baseline: %s" % json.dumps(cpu))
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": rep["iters"], "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16 matrix-core products, f32 accumulation, f64 Nystrom core",
+        "data": "synthetic (seeded Gaussian X, RFF prior-draw right-hand sides)",
+        "config": {"workload": "rbf_n%d_d%d_k%d" % (n, d, k), "n": n, "d": d, "k": k, "b": b,
+                   "r": r, "lambda": lam, "lengthscale": ell, "kernel": "rbf",
+                   "precision": "mixed"},
+        "time_to_relres_1e-3": ttr,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 1),
+                     "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_F16_MFMA_TFLOPS, 4), "traffic": None,
+                     "kernel": "mk_kernel (step-I kernel-block product)",
+                     "kernel_ms": round(kern_ms, 4),
+                     "algorithmic_flops_per_launch": flops_step1},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(X, Y, rows, ell, d, k, b, n):
+    """The float64 oracle's kernel-block product on `rows` block rows against all n points."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import kernels as OK
+    from oracle import rng as OR
+
+    Xh = X.double().cpu().numpy()
+    Yh = Y.double().cpu().numpy()
+    B = OR.sample_block(3, 0, n, b)[:rows]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        OK.kernel_matmul(Xh[B], Xh, Yh, OK.RBF, ell)
+        sec = time.perf_counter() - t0
+    flops = float(rows) * n * (2 * d + 2 * k)
+    return {"value": round(flops / sec / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "%d block rows x %d columns x %d right-hand sides of the step-I product "
+                      "(float64 numpy, one thread): %.2f s" % (rows, n, k, sec),
+            "seconds_per_step_extrapolated": round(sec * b / rows, 1)}
+
+
+if __name__ == "__main__":
+    main()

@@ -99,6 +99,10 @@ typedef struct {
   int32_t refine_done;     /* refinement sweeps performed */
   int32_t not_pd_events;   /* Nystrom cores that needed a shift increase */
   int32_t status;          /* adasap_status_t of the solve */
+  double step1_kernel_ms;  /* device time of the step-I kernel-block product kernels (matrix-core path) */
+  int64_t step1_launches;  /* number of those launches */
+  int32_t jacobi_sweeps_max; /* most sweeps one Nystrom eigendecomposition needed */
+  int32_t reserved;
 } adasap_report_t;
 
 typedef struct adasap_handle_s* adasap_handle_t;

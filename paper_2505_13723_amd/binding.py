@@ -52,6 +52,8 @@ class Report(ctypes.Structure):
         ("eta_last", ctypes.c_double), ("rho_last", ctypes.c_double),
         ("lambda_hat_last", ctypes.c_double), ("delta_last", ctypes.c_double),
         ("refine_done", ctypes.c_int32), ("not_pd_events", ctypes.c_int32), ("status", ctypes.c_int32),
+        ("step1_kernel_ms", ctypes.c_double), ("step1_launches", ctypes.c_int64),
+        ("jacobi_sweeps_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

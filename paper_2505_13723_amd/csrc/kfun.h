@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/adasap.h"
+
 namespace adasap {
 
 constexpr double LOG2E = 1.4426950408889634;

@@ -59,6 +59,70 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int splits, 
   P[e] = s;
 }
 
+// Gram products with a thin right factor (q <= 4): one thread per column of A, rows in
+// two interleaved halves, so every load of a row of A is coalesced.
+constexpr int GV_CHUNK = 512;
+__global__ __launch_bounds__(256) void gramv_partial_kernel(int64_t rows, int p, int q,
+                                                            const void* __restrict__ A, DT at,
+                                                            int64_t lda, const void* __restrict__ B,
+                                                            DT bt, int64_t ldb,
+                                                            double* __restrict__ part) {
+  __shared__ double red[128 * 4];
+  const int col = threadIdx.x % 128, half = threadIdx.x / 128;
+  const int64_t r0 = (int64_t)blockIdx.x * GV_CHUNK;
+  const int64_t r1 = r0 + GV_CHUNK < rows ? r0 + GV_CHUNK : rows;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (col < p) {
+    for (int64_t row = r0 + half; row < r1; row += 2) {
+      const double a = ld_any(A, at, row * lda + col);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < q) acc[c] += a * ld_any(B, bt, row * ldb + c);
+    }
+  }
+  if (half == 1)
+    for (int c = 0; c < 4; ++c) red[col * 4 + c] = acc[c];
+  __syncthreads();
+  if (half == 0 && col < p)
+    for (int c = 0; c < q; ++c) part[((int64_t)blockIdx.x * p + col) * q + c] = acc[c] + red[col * 4 + c];
+}
+
+// OUT = f E + A M for a thin M (q <= 4): one wave per row of A (p <= 128 entries)
+__global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int q,
+                                                        const double* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ M,
+                                                        double* __restrict__ out, int64_t ldo,
+                                                        const double* __restrict__ E, int64_t lde,
+                                                        const double* __restrict__ alpha_ptr,
+                                                        int alpha_mode) {
+  __shared__ double Ms[128 * 4];
+  for (int e = threadIdx.x; e < p * q; e += 256) Ms[e] = M[e];
+  __syncthreads();
+  const int lane = threadIdx.x % 64;
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= rows) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int l = lane; l < p; l += 64) {
+    const double a = A[row * lda + l];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < q) acc[c] += a * Ms[l * q + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
+  if (lane == 0) {
+    double f = 1.0;
+    if (alpha_mode == 1) f = 1.0 / *alpha_ptr;
+    else if (alpha_mode == 2) f = 1.0 / sqrt(*alpha_ptr);
+    for (int c = 0; c < q; ++c) {
+      double v = acc[c];
+      if (E) v += f * E[row * lde + c];
+      out[row * ldo + c] = v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- OUT = f(alpha) E + (A + delta A2) M
 constexpr int M_T = 32;
 __global__ __launch_bounds__(256) void gemm_rm_kernel(int64_t rows, int p, int q,
@@ -120,7 +184,7 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
                                                         double* __restrict__ Rinv,
                                                         double* __restrict__ Rg,
                                                         IterScalars* __restrict__ sc) {
-  __shared__ double C[RMAX * RMAX];
+  __shared__ double C[RMAX * (RMAX + 1)];
   __shared__ double xd[RMAX];
   __shared__ int flag;
   __shared__ double s_delta;
@@ -138,25 +202,25 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
     const double delta = s_delta;
     for (int e = tid; e < r * r; e += 1024) {
       const int i = e / r, j = e % r;
-      C[i * RMAX + j] = 0.5 * (Mo[i * r + j] + Mo[j * r + i]) + delta * Qo[i * r + j];
+      C[i * (RMAX + 1) + j] = 0.5 * (Mo[i * r + j] + Mo[j * r + i]) + delta * Qo[i * r + j];
     }
     __syncthreads();
     // right-looking Cholesky: C = R^T R, R upper, stored in the upper triangle of C
     for (int kk = 0; kk < r; ++kk) {
       if (tid == 0) {
-        const double piv = C[kk * RMAX + kk];
+        const double piv = C[kk * (RMAX + 1) + kk];
         if (!(piv > 0.0)) flag = 1;
-        else C[kk * RMAX + kk] = sqrt(piv);
+        else C[kk * (RMAX + 1) + kk] = sqrt(piv);
       }
       __syncthreads();
       if (flag) break;
-      const double dk = C[kk * RMAX + kk];
-      for (int j = kk + 1 + tid; j < r; j += 1024) C[kk * RMAX + j] /= dk;
+      const double dk = C[kk * (RMAX + 1) + kk];
+      for (int j = kk + 1 + tid; j < r; j += 1024) C[kk * (RMAX + 1) + j] /= dk;
       __syncthreads();
       const int w = r - kk - 1;
       for (int e = tid; e < w * w; e += 1024) {
         const int i = kk + 1 + e / w, j = kk + 1 + e % w;
-        if (j >= i) C[i * RMAX + j] -= C[kk * RMAX + i] * C[kk * RMAX + j];
+        if (j >= i) C[i * (RMAX + 1) + j] -= C[kk * (RMAX + 1) + i] * C[kk * (RMAX + 1) + j];
       }
       __syncthreads();
     }
@@ -186,7 +250,7 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
   if (Rg)
     for (int e = tid; e < r * r; e += 1024) {
       const int i = e / r, j = e % r;
-      Rg[e] = j >= i ? C[i * RMAX + j] : 0.0;
+      Rg[e] = j >= i ? C[i * (RMAX + 1) + j] : 0.0;
     }
   // X = R^{-1} (upper).  X[i][j] for i < j is kept in C[j][i] (strictly lower part),
   // X[j][j] in xd[j]; rows i are processed from the bottom, 8 threads per column j.
@@ -194,29 +258,34 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
   for (int i = r - 1; i >= 0; --i) {
     if (j < r && j >= i) {
       if (j == i) {
-        if (part == 0) xd[j] = 1.0 / C[i * RMAX + i];
+        if (part == 0) xd[j] = 1.0 / C[i * (RMAX + 1) + i];
       } else {
         double s = 0.0;
         for (int l = i + 1 + part; l <= j; l += 8) {
-          const double xl = (l == j) ? xd[j] : C[j * RMAX + l];
-          s += C[i * RMAX + l] * xl;
+          const double xl = (l == j) ? xd[j] : C[j * (RMAX + 1) + l];
+          s += C[i * (RMAX + 1) + l] * xl;
         }
         s += __shfl_xor(s, 1, 8);
         s += __shfl_xor(s, 2, 8);
         s += __shfl_xor(s, 4, 8);
-        if (part == 0) C[j * RMAX + i] = -s / C[i * RMAX + i];
+        if (part == 0) C[j * (RMAX + 1) + i] = -s / C[i * (RMAX + 1) + i];
       }
     }
     __syncthreads();
   }
   for (int e = tid; e < r * r; e += 1024) {
     const int a = e / r, b = e % r;
-    Rinv[e] = a == b ? xd[a] : (a < b ? C[b * RMAX + a] : 0.0);
+    Rinv[e] = a == b ? xd[a] : (a < b ? C[b * (RMAX + 1) + a] : 0.0);
   }
 }
 
 // ---------------------------------------------------------------- Jacobi eigensolver
-constexpr int JAC_MAX_SWEEPS = 20;
+// Parallel cyclic Jacobi: each step applies r/2 disjoint rotations (round-robin pairing),
+// H <- J^T H J, as independent 2x2-block updates (block (a, b) mixes rows of pair a with
+// columns of pair b), one LDS pass per step.  The row stride is padded to RMAX + 1 doubles
+// so that the column reads of a wave fall in different LDS banks.
+constexpr int JAC_MAX_SWEEPS = 16;
+constexpr int HS = RMAX + 1;  // padded row stride
 
 __device__ inline int rr_index(int i, int step, int rp) {
   // circle method: player 0 fixed, the others rotate by `step`
@@ -227,7 +296,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
                                                       double* __restrict__ evals,
                                                       double* __restrict__ rot,
                                                       IterScalars* __restrict__ sc) {
-  __shared__ double H[RMAX * RMAX];
+  __shared__ double H[RMAX * HS];
   __shared__ double cs_c[RMAX / 2], cs_s[RMAX / 2];
   __shared__ int pp[RMAX / 2], qq[RMAX / 2];
   __shared__ int nrot;
@@ -235,11 +304,15 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
   const int tid = threadIdx.x;
   const int rp = r + (r & 1);
   const int half = rp / 2;
-  for (int e = tid; e < r * r; e += 1024) H[(e / r) * RMAX + e % r] = Hg[e];
+  // the padded dummy index (odd r) has a zero row and column and is never rotated
+  for (int e = tid; e < rp * rp; e += 1024) {
+    const int i = e / rp, j = e % rp;
+    H[i * HS + j] = (i < r && j < r) ? Hg[i * r + j] : 0.0;
+  }
   __syncthreads();
   if (tid == 0) {
     double m = 0.0;
-    for (int i = 0; i < r; ++i) m = fmax(m, fabs(H[i * RMAX + i]));
+    for (int i = 0; i < r; ++i) m = fmax(m, fabs(H[i * HS + i]));
     hmax = m;
   }
   __syncthreads();
@@ -254,8 +327,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
         const int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, s = 0.0;
         if (q < r) {
-          const double apq = H[p * RMAX + q];
-          const double app = H[p * RMAX + p], aqq = H[q * RMAX + q];
+          const double apq = H[p * HS + q];
+          const double app = H[p * HS + p], aqq = H[q * HS + q];
           if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_floor)) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = fabs(tau) > 1e150 ? 0.5 / tau
@@ -274,33 +347,28 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
         rot[2 * slot + 1] = s;
       }
       __syncthreads();
-      // rows:  (H_p, H_q) <- (c H_p - s H_q, s H_p + c H_q)
-      for (int e = tid; e < half * r; e += 1024) {
-        const int k = e / r, jj = e % r;
-        const double s = cs_s[k];
-        if (s == 0.0) continue;
-        const double c = cs_c[k];
-        const int p = pp[k], q = qq[k];
-        const double hp = H[p * RMAX + jj], hq = H[q * RMAX + jj];
-        H[p * RMAX + jj] = c * hp - s * hq;
-        H[q * RMAX + jj] = s * hp + c * hq;
-      }
-      __syncthreads();
-      // columns
-      for (int e = tid; e < half * r; e += 1024) {
-        const int k = e / r, ii = e % r;
-        const double s = cs_s[k];
-        if (s == 0.0) continue;
-        const double c = cs_c[k];
-        const int p = pp[k], q = qq[k];
-        const double hp = H[ii * RMAX + p], hq = H[ii * RMAX + q];
-        H[ii * RMAX + p] = c * hp - s * hq;
-        H[ii * RMAX + q] = s * hp + c * hq;
-      }
-      __syncthreads();
-      if (tid < half && cs_s[tid] != 0.0) {
-        H[pp[tid] * RMAX + qq[tid]] = 0.0;
-        H[qq[tid] * RMAX + pp[tid]] = 0.0;
+      for (int e = tid; e < half * half; e += 1024) {
+        const int a = e / half, bb = e % half;
+        const double sa = cs_s[a], sb = cs_s[bb];
+        if (sa == 0.0 && sb == 0.0) continue;
+        const double ca = cs_c[a], cb = cs_c[bb];
+        const int pa = pp[a], qa = qq[a], pb = pp[bb], qb = qq[bb];
+        const double h11 = H[pa * HS + pb], h12 = H[pa * HS + qb];
+        const double h21 = H[qa * HS + pb], h22 = H[qa * HS + qb];
+        // rows: J_a^T
+        const double r11 = ca * h11 - sa * h21, r12 = ca * h12 - sa * h22;
+        const double r21 = sa * h11 + ca * h21, r22 = sa * h12 + ca * h22;
+        // columns: J_b
+        double n11 = cb * r11 - sb * r12, n12 = sb * r11 + cb * r12;
+        double n21 = cb * r21 - sb * r22, n22 = sb * r21 + cb * r22;
+        if (a == bb && sa != 0.0) {
+          n12 = 0.0;  // the rotation annihilates the pair's off-diagonal entry
+          n21 = 0.0;
+        }
+        H[pa * HS + pb] = n11;
+        H[pa * HS + qb] = n12;
+        H[qa * HS + pb] = n21;
+        H[qa * HS + qb] = n22;
       }
       __syncthreads();
     }
@@ -309,14 +377,14 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
     if (done == 0) break;
     sweeps_used = sweep + 1;
   }
-  for (int i = tid; i < r; i += 1024) evals[i] = H[i * RMAX + i];
+  for (int i = tid; i < r; i += 1024) evals[i] = H[i * HS + i];
   if (tid == 0) sc->sweeps = sweeps_used;
 }
 
-// V = J_1 J_2 ... applied to the identity; 8 rows of V per workgroup, one sweep of
-// rotations staged in LDS at a time.
-constexpr int ACC_ROWS = 8;
-__global__ __launch_bounds__(512) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
+// V = J_1 J_2 ... applied to the identity: ACC_ROWS rows of V per workgroup, one thread per
+// (row, pair); the rotations of one sweep are staged in LDS at a time.
+constexpr int ACC_ROWS = 4;
+__global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
                                                            const IterScalars* __restrict__ sc,
                                                            double* __restrict__ V) {
   __shared__ double Vs[ACC_ROWS][RMAX];
@@ -325,7 +393,7 @@ __global__ __launch_bounds__(512) void jacobi_accum_kernel(int r, const double* 
   const int rp = r + (r & 1);
   const int half = rp / 2;
   const int row0 = blockIdx.x * ACC_ROWS;
-  for (int e = tid; e < ACC_ROWS * RMAX; e += 512) {
+  for (int e = tid; e < ACC_ROWS * RMAX; e += 256) {
     const int a = e / RMAX, b = e % RMAX;
     Vs[a][b] = (row0 + a == b) ? 1.0 : 0.0;
   }
@@ -334,7 +402,7 @@ __global__ __launch_bounds__(512) void jacobi_accum_kernel(int r, const double* 
   const int ir = tid / 64, k = tid % 64;
   for (int sw = 0; sw < sweeps; ++sw) {
     __syncthreads();
-    for (int e = tid; e < 2 * per_sweep; e += 512) R[e] = rot[(int64_t)sw * 2 * per_sweep + e];
+    for (int e = tid; e < 2 * per_sweep; e += 256) R[e] = rot[(int64_t)sw * 2 * per_sweep + e];
     __syncthreads();
     for (int step = 0; step < rp - 1; ++step) {
       if (k < half && row0 + ir < r) {
@@ -352,7 +420,7 @@ __global__ __launch_bounds__(512) void jacobi_accum_kernel(int r, const double* 
     }
   }
   __syncthreads();
-  for (int e = tid; e < ACC_ROWS * r; e += 512) {
+  for (int e = tid; e < ACC_ROWS * r; e += 256) {
     const int a = e / r, b = e % r;
     if (row0 + a < r) V[(int64_t)(row0 + a) * r + b] = Vs[a][b];
   }
@@ -475,6 +543,22 @@ adasap_status_t woodbury_coefs(int r, const double* S, double rho, int power, do
 adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t lda, const void* B,
                      DT bt, int64_t ldb, double* P, const double* rowscale, DevBuf& part,
                      hipStream_t s) {
+  if (q <= 4 && p <= 128) {
+    int sp = (int)((rows + GV_CHUNK - 1) / GV_CHUNK);
+    if (sp < 1) sp = 1;
+    ADASAP_TRY(part.ensure((size_t)sp * p * q * sizeof(double)));
+    if (rows > 0) {
+      hipLaunchKernelGGL(gramv_partial_kernel, dim3(sp), dim3(256), 0, s, rows, p, q, A, at, lda, B,
+                         bt, ldb, part.as<double>());
+      ADASAP_LAUNCH_CHECK();
+    } else {
+      ADASAP_HIP(hipMemsetAsync(part.p, 0, (size_t)p * q * sizeof(double), s));
+    }
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256), dim3(256), 0, s,
+                       part.as<double>(), sp, p, q, rowscale, P);
+    ADASAP_LAUNCH_CHECK();
+    return ADASAP_OK;
+  }
   int splits = (int)((rows + G_CHUNK - 1) / G_CHUNK);
   if (splits < 1) splits = 1;
   ADASAP_TRY(part.ensure((size_t)splits * p * q * sizeof(double)));
@@ -493,6 +577,12 @@ adasap_status_t gemm_rm(int64_t rows, int p, int q, const double* A, const doubl
                         int64_t ldo, const double* E, int64_t lde, const double* alpha_ptr,
                         int alpha_mode, hipStream_t s) {
   if (rows <= 0) return ADASAP_OK;
+  if (q <= 4 && p <= 128 && A2 == nullptr) {
+    hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, p,
+                       q, A, lda, M, out, ldo, E, lde, alpha_ptr, alpha_mode);
+    ADASAP_LAUNCH_CHECK();
+    return ADASAP_OK;
+  }
   const dim3 grid((q + M_T - 1) / M_T, (unsigned)((rows + M_T - 1) / M_T));
   hipLaunchKernelGGL(gemm_rm_kernel, grid, dim3(256), 0, s, rows, p, q, A, A2, delta_ptr, lda, M,
                      out, ldo, E, lde, alpha_ptr, alpha_mode);
@@ -532,7 +622,7 @@ adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, dou
   }
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, r, H, evals, rot_buf, sc);
   ADASAP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_ROWS - 1) / ACC_ROWS), dim3(512), 0, s, r,
+  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_ROWS - 1) / ACC_ROWS), dim3(256), 0, s, r,
                      rot_buf, sc, V);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;

@@ -1,24 +1,788 @@
-// Matrix-core kernel-block products (placeholder until the gfx950 kernels land).
+// Matrix-core kernel-block products for gfx950 (v_mfma_f32_16x16x32_f16).
+//
+// Squared distances.  Points are centred (mean mu) and scaled by sigma, x~ = sigma (x - mu),
+// and split into float16 parts x~ = hi + lo.  With the norm term nx = |hi + lo|^2 / 2 split
+// into three float16 parts (n1 + n2 + n3 = -nx), a column vector
+//     [y_hi | y_lo | y_hi | ny1 ny2 ny3 | 1 1 1]
+// dotted with a row vector
+//     [x_hi | x_hi | x_lo | 1 1 1 | nx1 nx2 nx3]
+// gives y_hi.x_hi + y_lo.x_hi + y_hi.x_lo - ny - nx = -sigma^2 |x - y|^2 / 2 up to the
+// dropped lo.lo term (relative 2^-22), all on the matrix cores with float32 accumulation.
+// With sigma^2 = log2(e)/ell^2 this is the RBF exponent for exp2; with sigma^2 = 2/ell^2 it is
+// -(r/ell)^2 for the Matern family.  3d + 6 <= 32 needs one K-step of 32, d <= 16 two.
+//
+// Tiles.  A workgroup is 4 waves; each wave owns RT row tiles of 16 rows.  Columns stream
+// through LDS in tiles of 32 (double buffered).  For each 16x16 (column x row) block the
+// distance MFMA leaves lane l with columns 4(l/16)+0..3 of its column half and row l%16.
+// The eight kernel values of a lane (two column halves) form the B operand of the next MFMA
+// directly (K index = column slot), so the kernel block never leaves registers; the right-hand
+// side tile is stored pre-permuted in the matching slot order.
+//   MODE_F16   K and R in float16, one MFMA per (row tile, 16 right-hand sides)
+//   MODE_F16X3 K = K_hi + K_lo and R = R_hi + R_lo, three MFMAs (hi.hi + lo.hi + hi.lo)
+//   MODE_F32V  K in float32 times float32 R on the vector ALUs (k <= 4)
+// The column range is split over workgroups; partial sums are added in a fixed order.
+#include <cmath>
+
 #include "mfma.h"
+#include "kfun.h"
 
 namespace adasap {
 
-static adasap_status_t unsupported() {
-  set_error("MIXED precision kernels are not built yet");
-  return ADASAP_ERR_UNSUPPORTED;
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int TILE = 32;      // columns per tile
+constexpr int WAVES = 4;      // waves per workgroup
+constexpr int MODE_F16 = 0, MODE_F16X3 = 1, MODE_F32V = 2;
+constexpr int ROWVEC = 64;    // float16 entries stored per point (two K-steps)
+
+__device__ inline f4 mfma16(half8 a, half8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-size_t mfma_pack_bytes(int64_t, int, int) { return 0; }
-adasap_status_t mfma_pack_create(MfmaPack&, int64_t, int, int, const void*, DT, int, double,
-                                 hipStream_t) { return unsupported(); }
-size_t mfma_rhs_bytes(const MfmaPack&, int) { return 16; }
-adasap_status_t mfma_pack_rhs(const MfmaPack&, const void*, DT, int, void*, hipStream_t) { return unsupported(); }
-adasap_status_t mfma_kblock_rows(const MfmaPack&, int, double, int, const int64_t*, int64_t,
-                                 const void*, const void*, DT, int, void*, const KbEpilogue&,
-                                 DevBuf&, hipStream_t) { return unsupported(); }
-adasap_status_t mfma_kblock_points(const MfmaPack&, int, double, const void*, DT, int64_t,
-                                   const void*, int, void*, DT, DevBuf&, hipStream_t) { return unsupported(); }
-adasap_status_t mfma_residual(const MfmaPack&, int, double, const void*, DT, int, void*,
-                              const KbEpilogue&, DevBuf&, DevBuf&, hipStream_t) { return unsupported(); }
+// ---------------------------------------------------------------- packing
+__global__ void mean_partial_kernel(const void* __restrict__ X, DT xt, int64_t n, int d,
+                                    double* __restrict__ part) {
+  // block b sums rows [b*4096, ...) for every coordinate (thread f < d)
+  const int64_t r0 = (int64_t)blockIdx.x * 4096;
+  const int64_t r1 = r0 + 4096 < n ? r0 + 4096 : n;
+  for (int f = threadIdx.x; f < d; f += blockDim.x) {
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r)
+      s += xt == DT::F64 ? static_cast<const double*>(X)[r * d + f]
+                         : (double)static_cast<const float*>(X)[r * d + f];
+    part[(int64_t)blockIdx.x * d + f] = s;
+  }
+}
+
+__global__ void mean_final_kernel(const double* __restrict__ part, int nblk, int d, int64_t n,
+                                  double* __restrict__ mu) {
+  for (int f = threadIdx.x; f < d; f += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * d + f];
+    mu[f] = s / (double)n;
+  }
+}
+
+// row-format vectors of points (one thread per point); flag set if float16 would overflow
+__global__ void rowpack_kernel(const void* __restrict__ X, DT xt, int64_t n, int64_t npad, int d,
+                               const double* __restrict__ mu, double sigma,
+                               _Float16* __restrict__ rowv, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  _Float16* o = rowv + i * ROWVEC;
+  for (int e = 0; e < ROWVEC; ++e) o[e] = (_Float16)0.0f;
+  if (i >= n) return;
+  double nrm = 0.0;
+  bool bad = false;
+  for (int f = 0; f < d; ++f) {
+    const double x = xt == DT::F64 ? static_cast<const double*>(X)[i * d + f]
+                                   : (double)static_cast<const float*>(X)[i * d + f];
+    const double xs = sigma * (x - mu[f]);
+    bad |= !(fabs(xs) < 30000.0);
+    const _Float16 hi = (_Float16)(float)xs;
+    const _Float16 lo = (_Float16)(float)(xs - (double)(float)hi);
+    const double xh = (double)(float)hi + (double)(float)lo;
+    nrm += xh * xh;
+    o[f] = hi;
+    o[d + f] = hi;
+    o[2 * d + f] = lo;
+  }
+  const double nx = -0.5 * nrm;
+  bad |= !(fabs(nx) < 30000.0);
+  const _Float16 n1 = (_Float16)(float)nx;
+  const double r1 = nx - (double)(float)n1;
+  const _Float16 n2 = (_Float16)(float)r1;
+  const _Float16 n3 = (_Float16)(float)(r1 - (double)(float)n2);
+  o[3 * d + 0] = (_Float16)1.0f;
+  o[3 * d + 1] = (_Float16)1.0f;
+  o[3 * d + 2] = (_Float16)1.0f;
+  o[3 * d + 3] = n1;
+  o[3 * d + 4] = n2;
+  o[3 * d + 5] = n3;
+  if (bad) atomicOr(flag, 1);
+}
+
+// column A-fragments of the points idx[0..cnt) (identity if idx == null), from row vectors.
+// Column vector = [hi | lo | hi | n1 n2 n3 | 1 1 1]; fragment of tile T, half cs, K-step ks,
+// lane l holds column T*32 + cs*16 + l%16, entries ks*32 + 8(l/16) + 0..7.
+__global__ void colpack_kernel(const _Float16* __restrict__ rowv, const int64_t* __restrict__ idx,
+                               int64_t cnt, int64_t ntiles, int d, int KS,
+                               half8* __restrict__ colA) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one fragment per thread
+  const int64_t total = ntiles * 2 * KS * 64;
+  if (e >= total) return;
+  const int lane = (int)(e % 64);
+  const int ks = (int)((e / 64) % KS);
+  const int cs = (int)((e / (64 * KS)) % 2);
+  const int64_t T = e / (64 * KS * 2);
+  const int64_t c = T * TILE + cs * 16 + lane % 16;
+  half8 v;
+  if (c >= cnt) {
+    for (int j = 0; j < 8; ++j) v[j] = (_Float16)0.0f;
+  } else {
+    const _Float16* rv = rowv + (idx ? idx[c] : c) * ROWVEC;
+    for (int j = 0; j < 8; ++j) {
+      const int kk = ks * 32 + 8 * (lane / 16) + j;
+      _Float16 val = (_Float16)0.0f;
+      if (kk < d) val = rv[kk];                          // hi
+      else if (kk < 2 * d) val = rv[2 * d + (kk - d)];   // lo
+      else if (kk < 3 * d) val = rv[kk - 2 * d];         // hi
+      else if (kk < 3 * d + 3) val = rv[3 * d + 3 + (kk - 3 * d)];  // n1 n2 n3
+      else if (kk < 3 * d + 6) val = (_Float16)1.0f;
+      v[j] = val;
+    }
+  }
+  colA[e] = v;
+}
+
+// per-column maxima of |R| (rows x k, type rt), partials per 4096 rows; the block's threads
+// sweep the chunk in memory order and combine through integer maxima of the float bits
+// (non-negative floats order like their bit patterns)
+__global__ __launch_bounds__(256) void colmax_partial_kernel(const void* __restrict__ R, DT rt,
+                                                             int64_t rows, int k, int64_t ldr,
+                                                             float* __restrict__ part) {
+  __shared__ unsigned int mx[128];
+  for (int c = threadIdx.x; c < k; c += 256) mx[c] = 0u;
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * 4096;
+  const int64_t r1 = r0 + 4096 < rows ? r0 + 4096 : rows;
+  const int64_t cnt = (r1 - r0) * k;
+  if (256 % k == 0) {
+    // every element a thread visits lies in column threadIdx.x % k: keep the maximum in a register
+    float m = 0.0f;
+    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+      const int64_t row = r0 + e / k;
+      const int c = (int)(e % k);
+      const double v = rt == DT::F64 ? static_cast<const double*>(R)[row * ldr + c]
+                                     : (double)static_cast<const float*>(R)[row * ldr + c];
+      const float a = (float)fabs(v);
+      m = fmaxf(m, isfinite(a) ? a : 3.0e38f);
+    }
+    atomicMax(&mx[threadIdx.x % k], __float_as_uint(m));
+  } else {
+    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+      const int64_t row = r0 + e / k;
+      const int c = (int)(e % k);
+      const double v = rt == DT::F64 ? static_cast<const double*>(R)[row * ldr + c]
+                                     : (double)static_cast<const float*>(R)[row * ldr + c];
+      const float a = (float)fabs(v);
+      atomicMax(&mx[c], __float_as_uint(isfinite(a) ? a : 3.0e38f));
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += 256) part[(int64_t)blockIdx.x * k + c] = __uint_as_float(mx[c]);
+}
+
+// scale[c] = power of two with max|R[:, c]| / scale <= 2^14 (scale >= 2^-60), 1 if the column is 0
+__global__ void colmax_final_kernel(const float* __restrict__ part, int nblk, int k,
+                                    float* __restrict__ scale) {
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    float m = 0.0f;
+    for (int b = 0; b < nblk; ++b) m = fmaxf(m, part[(int64_t)b * k + c]);
+    float s = 1.0f;
+    if (m > 0.0f && isfinite(m)) {
+      int ex;
+      frexpf(m, &ex);             // m = f 2^ex, f in [0.5, 1)
+      int p = ex - 14;
+      if (p < -60) p = -60;
+      s = ldexpf(1.0f, p);
+    }
+    scale[c] = s;
+  }
+}
+
+// float16 right-hand-side fragments: tile T, tile q of 16 columns, part (hi, lo), lane, slot m
+// slot m of lane l is column 4(l/16)+m (m < 4) or 16+4(l/16)+m-4 of the tile
+__device__ inline int slot_col(int lane, int m) {
+  return m < 4 ? 4 * (lane / 16) + m : 16 + 4 * (lane / 16) + (m - 4);
+}
+
+__global__ void rhspack16_kernel(const void* __restrict__ R, DT rt, int64_t rows, int k,
+                                 int64_t ldr, const int64_t* __restrict__ idx,
+                                 const float* __restrict__ scale, int64_t ntiles, int NQ, int parts,
+                                 half8* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = ntiles * NQ * 64;
+  if (e >= total) return;
+  const int lane = (int)(e % 64);
+  const int q = (int)((e / 64) % NQ);
+  const int64_t T = e / (64 * NQ);
+  const int rhs = q * 16 + lane % 16;
+  half8 hi, lo;
+  const float inv = rhs < k ? 1.0f / scale[rhs] : 0.0f;
+  for (int m = 0; m < 8; ++m) {
+    const int64_t col = T * TILE + slot_col(lane, m);
+    float v = 0.0f;
+    if (col < rows && rhs < k) {
+      const int64_t src = idx ? idx[col] : col;
+      const double x = rt == DT::F64 ? static_cast<const double*>(R)[src * ldr + rhs]
+                                     : (double)static_cast<const float*>(R)[src * ldr + rhs];
+      v = (float)(x * (double)inv);
+    }
+    const _Float16 h = (_Float16)v;
+    hi[m] = h;
+    lo[m] = (_Float16)(v - (float)h);
+  }
+  const int64_t base = (T * NQ + q) * parts;
+  out[(base + 0) * 64 + lane] = hi;
+  if (parts == 2) out[(base + 1) * 64 + lane] = lo;
+}
+
+// float32 right-hand side, padded to ntiles*32 rows and KC columns
+template <int KC>
+__global__ void rhspack32_kernel(const void* __restrict__ R, DT rt, int64_t rows, int k,
+                                 int64_t ldr, const int64_t* __restrict__ idx, int64_t npad,
+                                 float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npad * KC) return;
+  const int64_t i = e / KC;
+  const int c = (int)(e % KC);
+  float v = 0.0f;
+  if (i < rows && c < k) {
+    const int64_t src = idx ? idx[i] : i;
+    v = rt == DT::F64 ? (float)static_cast<const double*>(R)[src * ldr + c]
+                      : static_cast<const float*>(R)[src * ldr + c];
+  }
+  out[e] = v;
+}
+
+// ---------------------------------------------------------------- the product kernel
+template <int KERN>
+__device__ inline float kval(float s, float p) {
+  // s = sigma-scaled exponent: RBF: exp2 argument; Matern: -(r/ell)^2
+  if constexpr (KERN == ADASAP_RBF) {
+    return __builtin_amdgcn_exp2f(s);
+  } else {
+    const float t = s < 0.0f ? -s : 0.0f;  // (r/ell)^2
+    const float a = __builtin_sqrtf(t) * p;   // p = 1, sqrt(3) or sqrt(5)
+    const float e = __builtin_amdgcn_exp2f(-a * 1.4426950408889634f);
+    if constexpr (KERN == ADASAP_MATERN12) return e;
+    else if constexpr (KERN == ADASAP_MATERN32) return (1.0f + a) * e;
+    else return (1.0f + a + a * a * (1.0f / 3.0f)) * e;
+  }
+}
+
+struct MkArgs {
+  const half8* colA;     // column fragments [ntiles][2][KS][64]
+  const half8* rowv;     // row vectors [points][8] (64 float16 each)
+  const int64_t* ridx;   // row point indices (null: rows 0..m-1)
+  int64_t m;             // rows
+  const void* rhs;       // packed right-hand side
+  int64_t ntiles;        // column tiles in total
+  int64_t tiles_per_split;
+  int splits;
+  int rwg;               // row workgroups
+  int xcd_map;           // 1: splits grouped by XCD
+  float* part;           // [splits][m][k]
+  int k;
+  float p;               // Matern factor
+};
+
+template <int MODE, int NQ>
+constexpr int mk_occupancy() { return 2; }
+
+template <int KS, int KERN, int MODE, int NQ, int RT>
+__global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkArgs a) {
+  // LDS: two buffers of (column fragments, right-hand-side fragments)
+  constexpr int A_FR = 2 * KS * 64;                                            // half8 per tile
+  constexpr int R_FR = MODE == MODE_F16 ? NQ * 64 : (MODE == MODE_F16X3 ? 2 * NQ * 64 : 0);
+  constexpr int R_F32 = MODE == MODE_F32V ? TILE * NQ : 0;                     // floats (NQ = KC)
+  constexpr int TOTAL16 = A_FR + R_FR + (R_F32 * 4) / 16;  // 16-byte words of one tile
+  constexpr int BUF_BYTES = ((TOTAL16 + 255) / 256) * 256 * 16;  // padded to whole load rounds
+  __shared__ __attribute__((aligned(16))) char lds[2 * BUF_BYTES];
+
+  const int tid = threadIdx.x;
+  const int lane = tid % 64;
+  const int wave = tid / 64;
+  const int bid = blockIdx.x;
+  int split, rw;
+  if (a.xcd_map) {
+    // workgroups are dealt round-robin to the 8 XCDs: keep every row workgroup of one column
+    // split on the same XCD so they share the split's column stream in that XCD's L2
+    const int xcd = bid % 8, local = bid / 8;
+    split = xcd + 8 * (local / a.rwg);
+    rw = local % a.rwg;
+  } else {
+    split = bid / a.rwg;
+    rw = bid % a.rwg;
+  }
+  const int64_t T0 = (int64_t)split * a.tiles_per_split;
+  int64_t T1 = T0 + a.tiles_per_split;
+  if (T1 > a.ntiles) T1 = a.ntiles;
+  const int64_t row_base = ((int64_t)rw * WAVES + wave) * RT * 16;
+
+  // row operands (constant over the column stream)
+  half8 Bfr[RT][KS];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = row_base + rt * 16 + lane % 16;
+    const int64_t pt = row < a.m ? (a.ridx ? a.ridx[row] : row) : (a.ridx ? a.ridx[0] : 0);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) Bfr[rt][ks] = a.rowv[pt * 8 + ks * 4 + lane / 16];
+  }
+  // consume the row fragments once here, so the loads are complete before the column stream
+  // starts and no wait for them lands inside the loop (where it would also wait for prefetches)
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) asm volatile("" ::"v"(Bfr[rt][ks]));
+
+  f4 acc[RT][MODE == MODE_F32V ? 1 : NQ];
+  float accv[RT][MODE == MODE_F32V ? NQ : 1];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+    for (int q = 0; q < (MODE == MODE_F32V ? 1 : NQ); ++q) acc[rt][q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < (MODE == MODE_F32V ? NQ : 1); ++c) accv[rt][c] = 0.f;
+  }
+
+  // cooperative tile loads (global -> registers -> LDS), two tiles ahead of the compute, one
+  // barrier per tile: while the waves compute tile T from one LDS buffer, tile T+1 is written
+  // to the other and tile T+2 is in flight in registers
+  constexpr int LOADS16 = (A_FR + R_FR + (R_F32 * 4) / 16 + 255) / 256;
+  uint4 stA[LOADS16], stB[LOADS16];
+  // branch-free loads (one basic block, so the wait before each LDS store covers exactly the
+  // older of the two register stages); lanes past the tile's data read a valid dummy address
+  auto gload = [&](uint4 (&st)[LOADS16], int64_t T) {
+    const uint4* ca = reinterpret_cast<const uint4*>(a.colA) + T * A_FR;
+    const uint4* rb = reinterpret_cast<const uint4*>(a.rhs) + T * (R_FR + (R_F32 * 4) / 16);
+#pragma unroll
+    for (int u = 0; u < LOADS16; ++u) {
+      const int e = tid + u * 256;
+      const uint4* src = e < A_FR ? ca + e : (e < TOTAL16 ? rb + (e - A_FR) : ca);
+      st[u] = *src;
+    }
+  };
+  auto sstore = [&](const uint4 (&st)[LOADS16], int buf) {
+    uint4* dst = reinterpret_cast<uint4*>(lds + buf * BUF_BYTES);
+#pragma unroll
+    for (int u = 0; u < LOADS16; ++u) dst[tid + u * 256] = st[u];
+  };
+  auto compute = [&](int buf) {
+    const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
+    half8 A[2][KS];
+#pragma unroll
+    for (int cs = 0; cs < 2; ++cs)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) A[cs][ks] = Af[(cs * KS + ks) * 64 + lane];
+
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      f4 S0 = f4{0.f, 0.f, 0.f, 0.f}, S1 = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        S0 = mfma16(A[0][ks], Bfr[rt][ks], S0);
+        S1 = mfma16(A[1][ks], Bfr[rt][ks], S1);
+      }
+      float kv[8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        kv[j] = kval<KERN>(S0[j], a.p);
+        kv[4 + j] = kval<KERN>(S1[j], a.p);
+      }
+      if constexpr (MODE == MODE_F32V) {
+        const float* zr = reinterpret_cast<const float*>(lds + buf * BUF_BYTES + A_FR * 16);
+        const int g = lane / 16;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int col = j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
+#pragma unroll
+          for (int c = 0; c < NQ; ++c) accv[rt][c] += kv[j] * zr[col * NQ + c];
+        }
+      } else {
+        half8 Kh;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Kh[j] = (_Float16)kv[j];
+        const half8* Rf = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES + A_FR * 16);
+        if constexpr (MODE == MODE_F16) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) acc[rt][q] = mfma16(Rf[q * 64 + lane], Kh, acc[rt][q]);
+        } else {
+          half8 Kl;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) Kl[j] = (_Float16)(kv[j] - (float)Kh[j]);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const half8 Rh = Rf[(q * 2 + 0) * 64 + lane];
+            const half8 Rl = Rf[(q * 2 + 1) * 64 + lane];
+            acc[rt][q] = mfma16(Rh, Kh, acc[rt][q]);
+            acc[rt][q] = mfma16(Rl, Kh, acc[rt][q]);
+            acc[rt][q] = mfma16(Rh, Kl, acc[rt][q]);
+          }
+        }
+      }
+    }
+  };
+
+  if (T0 < T1) {
+    // tiles past the end are clamped to the last one: loaded and stored but never computed
+    auto tc = [&](int64_t T) { return T < T1 ? T : T1 - 1; };
+    gload(stA, T0);
+    sstore(stA, 0);
+    gload(stB, tc(T0 + 1));
+    __syncthreads();
+    for (int64_t T = T0; T < T1; T += 2) {
+      // buffer 0 holds tile T; stB holds (or is receiving) tile T+1
+      gload(stA, tc(T + 2));
+      compute(0);
+      sstore(stB, 1);
+      __syncthreads();
+      if (T + 1 >= T1) break;
+      gload(stB, tc(T + 3));
+      compute(1);
+      sstore(stA, 0);
+      __syncthreads();
+    }
+  }
+
+  // write partial sums
+  float* part = a.part + (int64_t)split * a.m * a.k;
+  if constexpr (MODE == MODE_F32V) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        float v = accv[rt][c];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        const int64_t row = row_base + rt * 16 + lane % 16;
+        if (lane < 16 && row < a.m && c < a.k) part[row * a.k + c] = v;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t row = row_base + rt * 16 + lane % 16;
+      if (row >= a.m) continue;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rhs = q * 16 + 4 * (lane / 16) + j;
+          if (rhs < a.k) part[row * a.k + rhs] = acc[rt][q][j];
+        }
+    }
+  }
+}
+
+// out[i, c] = scale[c] * sum_s part[s, i, c] + epilogue
+__global__ void mk_reduce_kernel(const float* __restrict__ part, int splits, int64_t m, int k,
+                                 const float* __restrict__ scale, KbEpilogue ep,
+                                 void* __restrict__ out, DT ot) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * k) return;
+  const int64_t i = e / k;
+  const int c = (int)(e % k);
+  double s = 0.0;
+  for (int sp = 0; sp < splits; ++sp) s += (double)part[((int64_t)sp * m + i) * k + c];
+  if (scale) s *= (double)scale[c];
+  auto ld = [](const void* p, DT t, int64_t j) {
+    return t == DT::F64 ? static_cast<const double*>(p)[j] : (double)static_cast<const float*>(p)[j];
+  };
+  if (ep.E1) s += ep.a1 * ld(ep.E1, ep.e1t, (ep.e1idx ? ep.e1idx[i] : i) * ep.lde1 + c);
+  if (ep.E2) s += ep.a2 * ld(ep.E2, ep.e2t, (ep.e2idx ? ep.e2idx[i] : i) * ep.lde2 + c);
+  if (ot == DT::F64) static_cast<double*>(out)[e] = s;
+  else static_cast<float*>(out)[e] = (float)s;
+}
+
+// ---------------------------------------------------------------- dispatch
+template <int KS, int KERN, int MODE, int NQ, int RT>
+void launch_mk(const MkArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((mk_kernel<KS, KERN, MODE, NQ, RT>), dim3(grid), dim3(256), 0, s, a);
+}
+
+template <int KS, int KERN, int MODE>
+adasap_status_t disp_nq(const MkArgs& a, int nq, int grid, hipStream_t s) {
+  if constexpr (MODE == MODE_F32V) {
+    if (nq == 1) launch_mk<KS, KERN, MODE, 1, 4>(a, grid, s);
+    else if (nq == 2) launch_mk<KS, KERN, MODE, 2, 4>(a, grid, s);
+    else launch_mk<KS, KERN, MODE, 4, 4>(a, grid, s);
+  } else {
+    switch (nq) {
+      case 1: launch_mk<KS, KERN, MODE, 1, 4>(a, grid, s); break;
+      case 2: launch_mk<KS, KERN, MODE, 2, 4>(a, grid, s); break;
+      case 3: launch_mk<KS, KERN, MODE, 3, 4>(a, grid, s); break;
+      case 4: launch_mk<KS, KERN, MODE, 4, 4>(a, grid, s); break;
+      case 5: launch_mk<KS, KERN, MODE, 5, 2>(a, grid, s); break;
+      case 6: launch_mk<KS, KERN, MODE, 6, 2>(a, grid, s); break;
+      case 7: launch_mk<KS, KERN, MODE, 7, 2>(a, grid, s); break;
+      default: launch_mk<KS, KERN, MODE, 8, 2>(a, grid, s); break;
+    }
+  }
+  return ADASAP_OK;
+}
+
+template <int KS, int KERN>
+adasap_status_t disp_mode(const MkArgs& a, int mode, int nq, int grid, hipStream_t s) {
+  if (mode == MODE_F16) return disp_nq<KS, KERN, MODE_F16>(a, nq, grid, s);
+  if (mode == MODE_F16X3) return disp_nq<KS, KERN, MODE_F16X3>(a, nq, grid, s);
+  return disp_nq<KS, KERN, MODE_F32V>(a, nq, grid, s);
+}
+
+template <int KS>
+adasap_status_t disp_kern(const MkArgs& a, int kern, int mode, int nq, int grid, hipStream_t s) {
+  switch (kern) {
+    case ADASAP_RBF: return disp_mode<KS, ADASAP_RBF>(a, mode, nq, grid, s);
+    case ADASAP_MATERN12: return disp_mode<KS, ADASAP_MATERN12>(a, mode, nq, grid, s);
+    case ADASAP_MATERN32: return disp_mode<KS, ADASAP_MATERN32>(a, mode, nq, grid, s);
+    default: return disp_mode<KS, ADASAP_MATERN52>(a, mode, nq, grid, s);
+  }
+}
+
+inline int ksteps(int d) { return 3 * d + 6 <= 32 ? 1 : 2; }
+
+double sigma_for(int kern, double ell) {
+  return kern == ADASAP_RBF ? std::sqrt(LOG2E) / ell : std::sqrt(2.0) / ell;
+}
+
+float matern_factor(int kern) {
+  return kern == ADASAP_MATERN12 ? 1.0f : (kern == ADASAP_MATERN32 ? 1.7320508075688772f : 2.23606797749979f);
+}
+
+struct RhsDesc {
+  int mode;     // MODE_*
+  int nq;       // 16-column tiles (F16 modes) or KC (F32V)
+  const void* p;
+  const float* scale;  // null for F32V
+};
+
+// the product: rows (ridx into rowv, or rowv itself) x column fragments, into out (+ epilogue)
+adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
+                       const int64_t* ridx, int64_t m, int d, int kern, const RhsDesc& rd, int k,
+                       void* out, DT ot, const KbEpilogue& ep, DevBuf& part, hipStream_t s,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+  if (m <= 0) return ADASAP_OK;
+  const int RT = (rd.mode != MODE_F32V && rd.nq > 4) ? 2 : 4;
+  const int rows_per_wg = WAVES * RT * 16;
+  const int rwg = (int)((m + rows_per_wg - 1) / rows_per_wg);
+  // aim for >= 2048 workgroups (8 per CU) when the column range allows it
+  int splits = (2048 + rwg - 1) / rwg;
+  if (splits > ntiles) splits = (int)(ntiles > 0 ? ntiles : 1);
+  if (splits >= 8) splits -= splits % 8;
+  if (splits < 1) splits = 1;
+  int64_t tps = (ntiles + splits - 1) / splits;
+  if (tps < 1) tps = 1;
+  splits = (int)((ntiles + tps - 1) / tps);
+  if (splits < 1) splits = 1;
+  const int xcd_map = (splits % 8 == 0) ? 1 : 0;
+  ADASAP_TRY(part.ensure((size_t)splits * m * k * sizeof(float)));
+  MkArgs a;
+  a.colA = colA;
+  a.rowv = rowv;
+  a.ridx = ridx;
+  a.m = m;
+  a.rhs = rd.p;
+  a.ntiles = ntiles;
+  a.tiles_per_split = tps;
+  a.splits = splits;
+  a.rwg = rwg;
+  a.xcd_map = xcd_map;
+  a.part = part.as<float>();
+  a.k = k;
+  a.p = matern_factor(kern);
+  const int grid = rwg * splits;
+  const int KS = ksteps(d);
+  if (ev0) ADASAP_HIP(hipEventRecord(ev0, s));
+  if (KS == 1) ADASAP_TRY(disp_kern<1>(a, kern, rd.mode, rd.nq, grid, s));
+  else ADASAP_TRY(disp_kern<2>(a, kern, rd.mode, rd.nq, grid, s));
+  ADASAP_LAUNCH_CHECK();
+  if (ev1) ADASAP_HIP(hipEventRecord(ev1, s));
+  hipLaunchKernelGGL(mk_reduce_kernel, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, s,
+                     part.as<float>(), splits, m, k, rd.scale, ep, out, ot);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+// pack a right-hand side R (rows x k, type rt, optional row gather idx) for ntiles column tiles
+adasap_status_t pack_rhs(const void* R, DT rt, int64_t rows, int k, int64_t ldr,
+                         const int64_t* idx, int64_t ntiles, int mode, DevBuf& buf,
+                         DevBuf& scale, DevBuf& tmp, RhsDesc& rd, hipStream_t s) {
+  rd.mode = mode;
+  if (mode == MODE_F32V) {
+    const int kc = k == 1 ? 1 : (k == 2 ? 2 : 4);
+    const int64_t npad = ntiles * TILE;
+    ADASAP_TRY(buf.ensure((size_t)npad * kc * sizeof(float)));
+    const int64_t tot = npad * kc;
+    if (kc == 1)
+      hipLaunchKernelGGL(rhspack32_kernel<1>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R, rt, rows, k, ldr, idx, npad, buf.as<float>());
+    else if (kc == 2)
+      hipLaunchKernelGGL(rhspack32_kernel<2>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R, rt, rows, k, ldr, idx, npad, buf.as<float>());
+    else
+      hipLaunchKernelGGL(rhspack32_kernel<4>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R, rt, rows, k, ldr, idx, npad, buf.as<float>());
+    ADASAP_LAUNCH_CHECK();
+    rd.nq = kc;
+    rd.p = buf.p;
+    rd.scale = nullptr;
+    return ADASAP_OK;
+  }
+  const int nq = (k + 15) / 16;
+  const int parts = mode == MODE_F16X3 ? 2 : 1;
+  ADASAP_TRY(buf.ensure((size_t)ntiles * nq * parts * 64 * 16));
+  ADASAP_TRY(scale.ensure((size_t)k * sizeof(float)));
+  // column maxima of the (gathered) right-hand side
+  const int nblk = (int)((rows + 4095) / 4096);
+  ADASAP_TRY(tmp.ensure((size_t)(nblk > 0 ? nblk : 1) * k * sizeof(float)));
+  if (idx) {
+    // gathered rows: maxima over all of R are a valid (larger or equal) bound
+    set_error("internal: gathered float16 right-hand sides are packed from a contiguous copy");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  if (nblk > 0) {
+    hipLaunchKernelGGL(colmax_partial_kernel, dim3(nblk), dim3(256), 0, s, R, rt, rows, k, ldr,
+                       tmp.as<float>());
+    ADASAP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(colmax_final_kernel, dim3(1), dim3(128), 0, s, tmp.as<float>(), nblk, k,
+                     scale.as<float>());
+  ADASAP_LAUNCH_CHECK();
+  const int64_t tot = ntiles * nq * 64;
+  hipLaunchKernelGGL(rhspack16_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R, rt,
+                     rows, k, ldr, nullptr, scale.as<float>(), ntiles, nq, parts,
+                     buf.as<half8>());
+  ADASAP_LAUNCH_CHECK();
+  rd.nq = nq;
+  rd.p = buf.p;
+  rd.scale = scale.as<float>();
+  return ADASAP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- public launchers
+size_t mfma_pack_bytes(int64_t n, int d, int k) {
+  const int64_t nt = (n + TILE - 1) / TILE;
+  const int KS = ksteps(d);
+  return (size_t)nt * TILE * ROWVEC * 2 + (size_t)nt * 2 * KS * 64 * 16 +
+         (size_t)nt * ((k + 15) / 16) * 64 * 16;
+}
+
+adasap_status_t mfma_pack_create(MfmaPack& pk, int64_t n, int d, int k, const void* X, DT xt,
+                                 int kern, double ell, hipStream_t s) {
+  if (d < 1 || d > 16) {
+    set_error("matrix-core kernel-block products need 1 <= d <= 16");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  (void)k;
+  pk.n = n;
+  pk.d = d;
+  pk.kern = kern;
+  pk.ell = ell;
+  pk.ntiles = (n + TILE - 1) / TILE;
+  pk.sigma = sigma_for(kern, ell);
+  const int64_t npad = pk.ntiles * TILE;
+  const int KS = ksteps(d);
+  ADASAP_TRY(pk.centre.ensure((size_t)d * sizeof(double)));
+  ADASAP_TRY(pk.rowv.ensure((size_t)npad * ROWVEC * 2));
+  ADASAP_TRY(pk.cols.ensure((size_t)pk.ntiles * 2 * KS * 64 * 16));
+  ADASAP_TRY(pk.flag.ensure(sizeof(int)));
+  const int nblk = (int)((n + 4095) / 4096);
+  ADASAP_TRY(pk.tmp.ensure((size_t)(nblk > 0 ? nblk : 1) * d * sizeof(double)));
+  hipLaunchKernelGGL(mean_partial_kernel, dim3(nblk), dim3(64), 0, s, X, xt, n, d, pk.tmp.as<double>());
+  ADASAP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64), 0, s, pk.tmp.as<double>(), nblk, d, n,
+                     pk.centre.as<double>());
+  ADASAP_LAUNCH_CHECK();
+  ADASAP_HIP(hipMemsetAsync(pk.flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(rowpack_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, X, xt,
+                     n, npad, d, pk.centre.as<double>(), pk.sigma, pk.rowv.as<_Float16>(),
+                     pk.flag.as<int>());
+  ADASAP_LAUNCH_CHECK();
+  const int64_t nfr = pk.ntiles * 2 * KS * 64;
+  hipLaunchKernelGGL(colpack_kernel, dim3((unsigned)((nfr + 255) / 256)), dim3(256), 0, s,
+                     pk.rowv.as<_Float16>(), nullptr, n, pk.ntiles, d, KS, pk.cols.as<half8>());
+  ADASAP_LAUNCH_CHECK();
+  int flag = 0;
+  ADASAP_HIP(hipMemcpyAsync(&flag, pk.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  ADASAP_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    set_error("scaled coordinates exceed the float16 range of the matrix-core path "
+              "(lengthscale too small for the data spread); use FP32 or FP64 precision");
+    return ADASAP_ERR_UNSUPPORTED;
+  }
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_pack_block(const MfmaPack& pk, const int64_t* B, int64_t b, DevBuf& colsB,
+                                hipStream_t s) {
+  const int KS = ksteps(pk.d);
+  const int64_t nt = (b + TILE - 1) / TILE;
+  ADASAP_TRY(colsB.ensure((size_t)nt * 2 * KS * 64 * 16));
+  const int64_t nfr = nt * 2 * KS * 64;
+  hipLaunchKernelGGL(colpack_kernel, dim3((unsigned)((nfr + 255) / 256)), dim3(256), 0, s,
+                     pk.rowv.as<_Float16>(), B, b, nt, pk.d, KS, colsB.as<half8>());
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_product(const MfmaPack& pk, const int64_t* ridx, int64_t m,
+                             const void* colsB, int64_t ncols, const void* R, DT rt, int k,
+                             int mode, void* out, DT ot, const KbEpilogue& ep, MfmaWork& w,
+                             hipStream_t s) {
+  const bool all_cols = colsB == nullptr;
+  const int64_t nt = all_cols ? pk.ntiles : (ncols + TILE - 1) / TILE;
+  const int64_t rows = all_cols ? pk.n : ncols;
+  RhsDesc rd;
+  ADASAP_TRY(pack_rhs(R, rt, rows, k, k, nullptr, nt, mode, w.rhs, w.scale, w.tmp, rd, s));
+  return mk_run(all_cols ? pk.cols.as<half8>() : static_cast<const half8*>(colsB), nt,
+                pk.rowv.as<half8>(), ridx, m, pk.d, pk.kern, rd, k, out, ot, ep, w.part, s, w.ev0,
+                w.ev1);
+}
+
+adasap_status_t mfma_product_packed(const MfmaPack& pk, const int64_t* ridx, int64_t m,
+                                    const RhsPacked& rp, int k, void* out, DT ot,
+                                    const KbEpilogue& ep, MfmaWork& w, hipStream_t s) {
+  RhsDesc rd{rp.mode, rp.nq, rp.p, rp.scale};
+  return mk_run(pk.cols.as<half8>(), pk.ntiles, pk.rowv.as<half8>(), ridx, m, pk.d, pk.kern, rd,
+                k, out, ot, ep, w.part, s);
+}
+
+adasap_status_t mfma_pack_rhs_full(const MfmaPack& pk, const void* R, DT rt, int k, int mode,
+                                   MfmaWork& w, RhsPacked& rp, hipStream_t s) {
+  RhsDesc rd;
+  ADASAP_TRY(pack_rhs(R, rt, pk.n, k, k, nullptr, pk.ntiles, mode, w.rhs, w.scale, w.tmp, rd, s));
+  rp.mode = rd.mode;
+  rp.nq = rd.nq;
+  rp.p = rd.p;
+  rp.scale = rd.scale;
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_points(const MfmaPack& pk, const void* Xq, DT xt, int64_t m, DevBuf& rowq,
+                            hipStream_t s) {
+  const int64_t mpad = (m + 15) / 16 * 16;
+  ADASAP_TRY(rowq.ensure((size_t)mpad * ROWVEC * 2));
+  ADASAP_TRY(const_cast<MfmaPack&>(pk).flag.ensure(sizeof(int)));
+  ADASAP_HIP(hipMemsetAsync(pk.flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(rowpack_kernel, dim3((unsigned)((mpad + 255) / 256)), dim3(256), 0, s, Xq, xt,
+                     m, mpad, pk.d, pk.centre.as<double>(), pk.sigma, rowq.as<_Float16>(),
+                     pk.flag.as<int>());
+  ADASAP_LAUNCH_CHECK();
+  int flag = 0;
+  ADASAP_HIP(hipMemcpyAsync(&flag, pk.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  ADASAP_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    set_error("query points exceed the float16 range of the matrix-core path");
+    return ADASAP_ERR_UNSUPPORTED;
+  }
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_product_rows(const MfmaPack& pk, const void* rowq, int64_t m, const void* R,
+                                  DT rt, int k, int mode, void* out, DT ot, MfmaWork& w,
+                                  hipStream_t s) {
+  RhsDesc rd;
+  ADASAP_TRY(pack_rhs(R, rt, pk.n, k, k, nullptr, pk.ntiles, mode, w.rhs, w.scale, w.tmp, rd, s));
+  KbEpilogue none;
+  return mk_run(pk.cols.as<half8>(), pk.ntiles, static_cast<const half8*>(rowq), nullptr, m, pk.d,
+                pk.kern, rd, k, out, ot, none, w.part, s);
+}
+
+int mfma_mode_f16() { return MODE_F16; }
+int mfma_mode_f16x3() { return MODE_F16X3; }
+int mfma_mode_f32v() { return MODE_F32V; }
 
 }  // namespace adasap

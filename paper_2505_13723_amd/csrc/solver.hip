@@ -66,13 +66,25 @@ struct adasap_handle_s {
   // workspace
   DevBuf V, Z, Bdev, XB, G, D, Om, Ysk, Mo, Qo, Rinv, H, evals, Vr, T, S, cinv, cisq, Bm, U, rot;
   DevBuf vv, ww, uu, zz, coef, part_kb, part_g, part_d, scb, tail, res, rhs, delta_w, tmp, colq;
-  DevBuf zpack;  // float16 copy of Z for the matrix-core kernel
+  MfmaWork mw;    // matrix-core scratch of the main stream
+  MfmaWork mw2;   // matrix-core scratch of the second stream (sketch, powering)
+  DevBuf part_kb2, part_g2, coef2;  // second-stream scratch
+  hipStream_t s2 = nullptr;         // second stream (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  DevBuf colsB;   // column fragments of the current block
+  DevBuf rowq;    // row vectors of prediction points
   int64_t* Bhost[2] = {nullptr, nullptr};
   hipEvent_t bev[2] = {nullptr, nullptr};
   IterScalars* sc_host = nullptr;  // pinned trace of per-iteration scalars
   int64_t sc_host_cap = 0;
   std::vector<double> eta_tr, rho_tr, lh_tr;
+  std::vector<hipEvent_t> kev;  // event pairs around the step-I product kernel
+  int64_t kev_used = 0;
   ~adasap_handle_s() {
+    for (hipEvent_t e : kev) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (s2) (void)hipStreamDestroy(s2);
     for (int i = 0; i < 2; ++i) {
       if (Bhost[i]) (void)hipHostFree(Bhost[i]);
       if (bev[i]) (void)hipEventDestroy(bev[i]);
@@ -133,22 +145,21 @@ double sketch_eps(int prec) { return prec == ADASAP_FP64 ? std::ldexp(1.0, -52) 
 adasap_status_t hk_kblock(adasap_handle_t h, int64_t m, int64_t n, const void* Xr,
                           const int64_t* ridx, DT xt, const void* Xc, const void* R, DT rt,
                           int64_t ldr, int kk, void* out, DT ot, int64_t ldo, const KbEpilogue& ep,
-                          bool cols_are_X, int prec) {
+                          int prec, hipStream_t st, DevBuf& part) {
   return kblock_valu(h->cfg.kernel, h->cfg.lengthscale, prec, m, n, h->d, kk, Xr, ridx, xt, Xc, R,
-                     rt, ldr, out, ot, ldo, ep, h->part_kb, h->s);
-  (void)cols_are_X;
+                     rt, ldr, out, ot, ldo, ep, part, st);
 }
 
 // P^{-1} X (power 0) or P^{-1/2} X (power 1) for the current Nystrom factors; X, out b x kk
 adasap_status_t precond_apply_h(adasap_handle_t h, int kk, const double* Xin, double* out,
-                                int power) {
+                                int power, hipStream_t st, DevBuf& part, DevBuf& coef) {
   const int64_t b = h->cfg.block_size;
   const int r = h->cfg.rank;
   IterScalars* sc = h->scb.as<IterScalars>();
-  ADASAP_TRY(gram(b, r, kk, h->U.p, DT::F64, r, Xin, DT::F64, kk, h->coef.as<double>(),
-                  power == 0 ? h->cinv.as<double>() : h->cisq.as<double>(), h->part_g, h->s));
-  return gemm_rm(b, r, kk, h->U.as<double>(), nullptr, nullptr, r, h->coef.as<double>(), out, kk,
-                 Xin, kk, &sc->rho, power == 0 ? 1 : 2, h->s);
+  ADASAP_TRY(gram(b, r, kk, h->U.p, DT::F64, r, Xin, DT::F64, kk, coef.as<double>(),
+                  power == 0 ? h->cinv.as<double>() : h->cisq.as<double>(), part, st));
+  return gemm_rm(b, r, kk, h->U.as<double>(), nullptr, nullptr, r, coef.as<double>(), out, kk,
+                 Xin, kk, &sc->rho, power == 0 ? 1 : 2, st);
 }
 
 // one ADASAP iteration; rhs is the current right-hand side (Y or a refinement residual)
@@ -169,7 +180,12 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   ADASAP_HIP(hipMemcpyAsync(h->Bdev.p, h->Bhost[slot], b * sizeof(int64_t), hipMemcpyHostToDevice, s));
   ADASAP_HIP(hipEventRecord(h->bev[slot], s));
   const int64_t* B = h->Bdev.as<int64_t>();
-  ADASAP_TRY(gather_rows(b, d, h->X, h->dtype, d, B, h->XB.p, h->dtype, d, s));
+  if (!h->use_mfma) ADASAP_TRY(gather_rows(b, d, h->X, h->dtype, d, B, h->XB.p, h->dtype, d, s));
+  // the sketch, the Nystrom factors and the step size do not depend on the block gradient:
+  // they run on a second stream while the main stream evaluates K_{B,:} Z
+  hipStream_t s2 = h->s2;
+  ADASAP_HIP(hipEventRecord(h->ev_fork, s));
+  ADASAP_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
 
   // gradient block at Z (accelerated; the reading of Alg. 2 Step IV), at W_t (accelerated,
   // printed form) or at the iterate (plain steps keep the iterate in Z)
@@ -188,50 +204,68 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   epg.lde2 = k;
   epg.a2 = -1.0;
   if (h->use_mfma) {
-    ADASAP_TRY(mfma_kblock_rows(h->pack, c.kernel, c.lengthscale, prec, B, b, h->zpack.p, h->Z.p,
-                                h->st, k, h->G.p, epg, h->part_kb, s));
+    const int mode = prec == ADASAP_MIXED ? mfma_mode_f16() : (k <= 4 ? mfma_mode_f32v() : mfma_mode_f16x3());
+    if ((int64_t)h->kev.size() < 2 * (h->kev_used + 1)) {
+      for (int e = 0; e < 2; ++e) {
+        hipEvent_t ev;
+        ADASAP_HIP(hipEventCreate(&ev));
+        h->kev.push_back(ev);
+      }
+    }
+    h->mw.ev0 = h->kev[2 * h->kev_used];
+    h->mw.ev1 = h->kev[2 * h->kev_used + 1];
+    ++h->kev_used;
+    const adasap_status_t pst = mfma_product(h->pack, B, b, nullptr, 0, gp, gt, k, mode, h->G.p,
+                                             DT::F64, epg, h->mw, s);
+    h->mw.ev0 = h->mw.ev1 = nullptr;
+    ADASAP_TRY(pst);
+    ADASAP_TRY(mfma_pack_block(h->pack, B, b, h->colsB, s2));
   } else {
     ADASAP_TRY(hk_kblock(h, b, n, h->X, B, h->dtype, h->X, gp, gt, k, k, h->G.p, DT::F64, k,
-                         epg, true, kprec));
+                         epg, kprec, s, h->part_kb));
   }
 
   const bool nys = c.precond == ADASAP_PRECOND_NYSTROM;
   if (nys) {
     // Step II: sketch
-    ADASAP_TRY(normals_dev(c.seed, PURPOSE_OMEGA + off, (uint64_t)t, b * r, h->Om.as<double>(), s));
+    ADASAP_TRY(normals_dev(c.seed, PURPOSE_OMEGA + off, (uint64_t)t, b * r, h->Om.as<double>(), s2));
     KbEpilogue none;
-    ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, h->Om.p, DT::F64, r, r,
-                         h->Ysk.p, DT::F64, r, none, false, kprec));
+    if (h->use_mfma)
+      ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, h->Om.p, DT::F64, r, mfma_mode_f16x3(),
+                              h->Ysk.p, DT::F64, none, h->mw2, s2));
+    else
+      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, h->Om.p, DT::F64, r, r,
+                           h->Ysk.p, DT::F64, r, none, kprec, s2, h->part_kb2));
     // Step III: Nystrom factors
     ADASAP_TRY(gram(b, r, r, h->Om.p, DT::F64, r, h->Ysk.p, DT::F64, r, h->Mo.as<double>(), nullptr,
-                    h->part_g, s));
+                    h->part_g2, s2));
     ADASAP_TRY(gram(b, r, r, h->Om.p, DT::F64, r, h->Om.p, DT::F64, r, h->Qo.as<double>(), nullptr,
-                    h->part_g, s));
+                    h->part_g2, s2));
     ADASAP_TRY(nys_core(r, h->Mo.as<double>(), h->Qo.as<double>(), sketch_eps(prec),
-                        h->Rinv.as<double>(), nullptr, sc, s));
+                        h->Rinv.as<double>(), nullptr, sc, s2));
     ADASAP_TRY(gemm_rm(b, r, r, h->Ysk.as<double>(), h->Om.as<double>(), &sc->delta, r,
-                       h->Rinv.as<double>(), h->Bm.as<double>(), r, nullptr, 0, nullptr, 0, s));
+                       h->Rinv.as<double>(), h->Bm.as<double>(), r, nullptr, 0, nullptr, 0, s2));
     ADASAP_TRY(gram(b, r, r, h->Bm.p, DT::F64, r, h->Bm.p, DT::F64, r, h->H.as<double>(), nullptr,
-                    h->part_g, s));
+                    h->part_g2, s2));
     ADASAP_TRY(jacobi_eig(r, h->H.as<double>(), h->evals.as<double>(), h->Vr.as<double>(),
-                          h->rot.as<double>(), sc, s));
+                          h->rot.as<double>(), sc, s2));
     ADASAP_TRY(nys_finalize(r, h->evals.as<double>(), h->Vr.as<double>(), c.rho_rule, c.lambda,
                             c.rho, h->S.as<double>(), h->T.as<double>(), h->cinv.as<double>(),
-                            h->cisq.as<double>(), sc, s));
+                            h->cisq.as<double>(), sc, s2));
     ADASAP_TRY(gemm_rm(b, r, r, h->Bm.as<double>(), nullptr, nullptr, r, h->T.as<double>(),
-                       h->U.as<double>(), r, nullptr, 0, nullptr, 0, s));
+                       h->U.as<double>(), r, nullptr, 0, nullptr, 0, s2));
   }
   // step size by randomized powering
   double* v = h->vv.as<double>();
   double* w = h->ww.as<double>();
   double* u = h->uu.as<double>();
   double* z = h->zz.as<double>();
-  ADASAP_TRY(normals_dev(c.seed, PURPOSE_POW + off, (uint64_t)t, b, v, s));
-  ADASAP_TRY(normalize_inplace(b, v, sc, h->part_d, s));
+  ADASAP_TRY(normals_dev(c.seed, PURPOSE_POW + off, (uint64_t)t, b, v, s2));
+  ADASAP_TRY(normalize_inplace(b, v, sc, h->part_d, s2));
   for (int i = 0; i < c.power_iters; ++i) {
     const double* win = v;
     if (nys) {
-      ADASAP_TRY(precond_apply_h(h, 1, v, w, 1));
+      ADASAP_TRY(precond_apply_h(h, 1, v, w, 1, s2, h->part_g2, h->coef2));
       win = w;
     }
     KbEpilogue epp;
@@ -239,26 +273,32 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
     epp.e1t = DT::F64;
     epp.lde1 = 1;
     epp.a1 = c.lambda;
-    ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, win, DT::F64, 1, 1, u,
-                         DT::F64, 1, epp, false, kprec));
+    if (h->use_mfma)
+      ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, win, DT::F64, 1, mfma_mode_f32v(), u,
+                              DT::F64, epp, h->mw2, s2));
+    else
+      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, win, DT::F64, 1, 1, u,
+                           DT::F64, 1, epp, kprec, s2, h->part_kb2));
     const double* zin = u;
     if (nys) {
-      ADASAP_TRY(precond_apply_h(h, 1, u, z, 1));
+      ADASAP_TRY(precond_apply_h(h, 1, u, z, 1, s2, h->part_g2, h->coef2));
       zin = z;
     }
-    ADASAP_TRY(dots_vz(b, v, zin, sc, h->part_d, s));
-    ADASAP_TRY(normalize_into(b, zin, v, sc, i == c.power_iters - 1 ? 1 : 0, s));
+    ADASAP_TRY(dots_vz(b, v, zin, sc, h->part_d, s2));
+    ADASAP_TRY(normalize_into(b, zin, v, sc, i == c.power_iters - 1 ? 1 : 0, s2));
   }
+  // join: the direction needs both the block gradient and the Nystrom factors
+  ADASAP_HIP(hipEventRecord(h->ev_join, s2));
+  ADASAP_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
   // Step IV: direction and update
   const double* Dp = h->G.as<double>();
   if (nys) {
-    ADASAP_TRY(precond_apply_h(h, k, h->G.as<double>(), h->D.as<double>(), 0));
+    ADASAP_TRY(precond_apply_h(h, k, h->G.as<double>(), h->D.as<double>(), 0, s, h->part_g, h->coef));
     Dp = h->D.as<double>();
   }
   if (c.accel) ADASAP_TRY(nesterov_dense(n * k, h->V.p, h->Z.p, h->st, h->nc, Wout, h->dtype, s));
   ADASAP_TRY(nesterov_sparse(b, k, B, Dp, h->V.p, h->Z.p, h->st, h->nc, sc, c.accel ? Wout : nullptr,
                              h->dtype, s));
-  if (h->use_mfma) ADASAP_TRY(mfma_pack_rhs(h->pack, h->Z.p, h->st, k, h->zpack.p, s));
   return ADASAP_OK;
 }
 
@@ -278,11 +318,11 @@ adasap_status_t residual_h(adasap_handle_t h, const void* W, DT wt, const void* 
   ep.lde2 = k;
   ep.a2 = -1.0;
   if (h->use_mfma) {
-    ADASAP_TRY(mfma_residual(h->pack, h->cfg.kernel, h->cfg.lengthscale, W, wt, k, h->res.p, ep,
-                             h->part_kb, h->tmp, h->s));
+    ADASAP_TRY(mfma_product(h->pack, nullptr, n, nullptr, 0, W, wt, k, mfma_mode_f16x3(), h->res.p,
+                            DT::F64, ep, h->mw, h->s));
   } else {
     ADASAP_TRY(hk_kblock(h, n, n, h->X, nullptr, h->dtype, h->X, W, wt, k, k, h->res.p, DT::F64, k,
-                         ep, true, ADASAP_FP64));
+                         ep, ADASAP_FP64, h->s, h->part_kb));
   }
   double* cq = h->colq.as<double>();
   ADASAP_TRY(colsq(n, k, h->res.p, DT::F64, k, cq, h->tmp, h->s));
@@ -309,9 +349,23 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
                           double& check_ms, int64_t& trace_pos) {
   const adasap_config_t& c = h->cfg;
   const int64_t nk = h->n * h->k;
+  // device time of the iterations: one event pair per segment between residual checks;
+  // nothing synchronises inside a segment, so the host samples the next block while the
+  // device works
   hipEvent_t e0, e1;
   ADASAP_HIP(hipEventCreate(&e0));
   ADASAP_HIP(hipEventCreate(&e1));
+  bool seg_open = false;
+  auto close_segment = [&]() -> adasap_status_t {
+    if (!seg_open) return ADASAP_OK;
+    ADASAP_HIP(hipEventRecord(e1, h->s));
+    ADASAP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    ADASAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    solve_ms += ms;
+    seg_open = false;
+    return ADASAP_OK;
+  };
   const bool tail = c.tail_average != 0;
   int64_t tail_count = 0;
   if (tail) {
@@ -327,21 +381,20 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
     }
     const bool check_now = every > 0 && ((t + 1) % every == 0 || t + 1 == T);
     const bool need_w = tail || check_now || t + 1 == T || (c.accel && !c.grad_at_z);
-    ADASAP_HIP(hipEventRecord(e0, h->s));
+    if (!seg_open) {
+      ADASAP_HIP(hipEventRecord(e0, h->s));
+      seg_open = true;
+    }
     ADASAP_TRY(iterate(h, t, off, rhs, rhst, need_w || !c.accel ? W : nullptr));
-    ADASAP_HIP(hipEventRecord(e1, h->s));
     if (trace_pos < h->sc_host_cap) {
       ADASAP_HIP(hipMemcpyAsync(h->sc_host + trace_pos, h->scb.p, sizeof(IterScalars),
                                 hipMemcpyDeviceToHost, h->s));
     }
     ++trace_pos;
     ++iters_done;
-    ADASAP_HIP(hipEventSynchronize(e1));
-    float ms = 0;
-    ADASAP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    solve_ms += ms;
     if (!c.accel && need_w) ADASAP_TRY(convert(nk, h->Z.p, h->st, W, h->dtype, h->s));
     if (check_now) {
+      ADASAP_TRY(close_segment());
       auto c0 = std::chrono::steady_clock::now();
       ADASAP_TRY(residual_h(h, W, h->dtype, rhs, rhst, &relres, &relmax, false));
       check_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
@@ -354,6 +407,7 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
       if (relres <= c.tol) break;
     }
   }
+  ADASAP_TRY(close_segment());
   if (!c.accel) ADASAP_TRY(convert(nk, h->Z.p, h->st, W, h->dtype, h->s));
   if (tail && tail_count > 0)
     ADASAP_TRY(scale_store(nk, h->tail.as<double>(), 1.0 / (double)tail_count, W, h->dtype, h->s));
@@ -406,7 +460,7 @@ int64_t adasap_workspace_bytes(const adasap_config_t* cfg, int64_t n, int32_t d,
   int64_t bytes = 2 * n * k * st;                       // V, Z
   bytes += b * (8 + 8 * d + 16 * k + 24 * r + 32);      // B, X_B, G, D, Omega, Y_sk, B, U, vectors
   bytes += 8 * r * r * 8 + 8 * (int64_t)jacobi_rot_capacity((int)r);
-  if (cfg->precision == ADASAP_MIXED) bytes += mfma_pack_bytes(n, d, k);
+  if (cfg->precision != ADASAP_FP64 && d <= 16) bytes += mfma_pack_bytes(n, d, k);
   return bytes;
 }
 
@@ -436,7 +490,8 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   h->nc.alpha = 1.0 / (1.0 + h->nc.gamma * h->nu);
   h->nc.accel = cfg->accel ? 1 : 0;
   h->nc.z_uses_v_next = cfg->z_uses_v_next ? 1 : 0;
-  h->use_mfma = cfg->precision == ADASAP_MIXED;
+  // matrix-core products for the reduced precisions whenever the coordinates fit them
+  h->use_mfma = cfg->precision != ADASAP_FP64 && d <= 16;
   auto fail = [&](adasap_status_t st) {
     delete h;
     return st;
@@ -468,6 +523,7 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   ENS(cinv, r * 8);
   ENS(cisq, r * 8);
   ENS(coef, (size_t)r * (k > 1 ? k : 1) * 8);
+  ENS(coef2, (size_t)r * 8);
   ENS(rot, jacobi_rot_capacity(r) * 8);
   ENS(vv, b * 8);
   ENS(ww, b * 8);
@@ -481,15 +537,21 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
     return fail(ADASAP_ERR_OOM);
   }
   if (hipEventCreateWithFlags(&h->bev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->bev[1], hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->bev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking) != hipSuccess) {
     set_error("event creation failed");
     return fail(ADASAP_ERR_DEVICE);
   }
   if (hipMemsetAsync(h->scb.p, 0, sizeof(IterScalars), h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
   if (h->use_mfma) {
-    if ((st = mfma_pack_create(h->pack, n, d, k, X, h->dtype, cfg->kernel, cfg->lengthscale, h->s)) != ADASAP_OK)
+    st = mfma_pack_create(h->pack, n, d, k, X, h->dtype, cfg->kernel, cfg->lengthscale, h->s);
+    if (st == ADASAP_ERR_UNSUPPORTED && cfg->precision == ADASAP_FP32) {
+      h->use_mfma = false;  // coordinates outside the float16 range: vector-ALU products
+    } else if (st != ADASAP_OK) {
       return fail(st);
-    if ((st = h->zpack.ensure(mfma_rhs_bytes(h->pack, k))) != ADASAP_OK) return fail(st);
+    }
   }
   if (hipStreamSynchronize(h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
   *out = h;
@@ -529,8 +591,8 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
   // V_0 = Z_0 = W_0
   ADASAP_TRY(convert(nk, W, h->dtype, h->V.p, h->st, h->s));
   ADASAP_TRY(convert(nk, W, h->dtype, h->Z.p, h->st, h->s));
-  if (h->use_mfma) ADASAP_TRY(mfma_pack_rhs(h->pack, h->Z.p, h->st, h->k, h->zpack.p, h->s));
   int64_t trace_pos = 0;
+  h->kev_used = 0;
   double relres = -1, relmax = -1;
   ADASAP_TRY(run_sweep(h, 0, h->Y, h->dtype, W, rep.iters, relres, relmax, rep.solve_ms,
                        rep.check_ms, trace_pos));
@@ -545,7 +607,6 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
     ADASAP_HIP(hipMemsetAsync(h->delta_w.p, 0, (size_t)nk * dt_size(h->dtype), h->s));
     ADASAP_HIP(hipMemsetAsync(h->V.p, 0, (size_t)nk * dt_size(h->st), h->s));
     ADASAP_HIP(hipMemsetAsync(h->Z.p, 0, (size_t)nk * dt_size(h->st), h->s));
-    if (h->use_mfma) ADASAP_TRY(mfma_pack_rhs(h->pack, h->Z.p, h->st, h->k, h->zpack.p, h->s));
     double r2 = -1, m2 = -1;
     ADASAP_TRY(run_sweep(h, PURPOSE_SWEEP_STRIDE * (uint64_t)sw, h->rhs.p, DT::F64, h->delta_w.p,
                          rep.iters, r2, m2, rep.solve_ms, rep.check_ms, trace_pos));
@@ -568,6 +629,7 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
     h->rho_tr[i] = h->sc_host[i].rho;
     h->lh_tr[i] = h->sc_host[i].lam_hat;
     rep.not_pd_events += h->sc_host[i].not_pd;
+    if (h->sc_host[i].sweeps > rep.jacobi_sweeps_max) rep.jacobi_sweeps_max = h->sc_host[i].sweeps;
     if (h->sc_host[i].failed) {
       set_error("Nystrom core not positive definite after shift retries");
       rep.status = ADASAP_ERR_NOT_PD;
@@ -581,6 +643,11 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
   }
   rep.relres = relres;
   rep.relres_maxcol = relmax;
+  for (int64_t i = 0; i < h->kev_used; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, h->kev[2 * i], h->kev[2 * i + 1]) == hipSuccess) rep.step1_kernel_ms += ms;
+  }
+  rep.step1_launches = h->kev_used;
   if (report) *report = rep;
   return rep.status == ADASAP_OK ? ADASAP_OK : (adasap_status_t)rep.status;
 }
@@ -593,8 +660,14 @@ adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, cons
   if (!W || !Xstar || !out) return invalid("W, Xstar and out must be non-null device pointers");
   KbEpilogue none;
   const int kprec = h->cfg.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
-  ADASAP_TRY(hk_kblock(h, m, h->n, Xstar, nullptr, h->dtype, h->X, W, h->dtype, h->k, h->k, out,
-                       h->dtype, h->k, none, true, kprec));
+  if (h->use_mfma) {
+    ADASAP_TRY(mfma_points(h->pack, Xstar, h->dtype, m, h->rowq, h->s));
+    ADASAP_TRY(mfma_product_rows(h->pack, h->rowq.p, m, W, h->dtype, h->k, mfma_mode_f16x3(), out,
+                                 h->dtype, h->mw, h->s));
+  } else {
+    ADASAP_TRY(hk_kblock(h, m, h->n, Xstar, nullptr, h->dtype, h->X, W, h->dtype, h->k, h->k, out,
+                         h->dtype, h->k, none, kprec, h->s, h->part_kb));
+  }
   ADASAP_HIP(hipStreamSynchronize(h->s));
   return ADASAP_OK;
 }
@@ -662,11 +735,11 @@ adasap_status_t adasap_kblock_matmul(int32_t kernel, double lengthscale, int32_t
   const DT t = to_dt(dtype);
   if (precision == ADASAP_MIXED && n > 0) {
     MfmaPack pk;
+    MfmaWork w;
+    DevBuf rowq;
     ADASAP_TRY(mfma_pack_create(pk, n, d, k, Xc, t, kernel, lengthscale, s));
-    DevBuf zp;
-    ADASAP_TRY(zp.ensure(mfma_rhs_bytes(pk, k)));
-    ADASAP_TRY(mfma_pack_rhs(pk, R, t, k, zp.p, s));
-    ADASAP_TRY(mfma_kblock_points(pk, kernel, lengthscale, Xr, t, m, zp.p, k, out, t, part, s));
+    ADASAP_TRY(mfma_points(pk, Xr, t, m, rowq, s));
+    ADASAP_TRY(mfma_product_rows(pk, rowq.p, m, R, t, k, mfma_mode_f16(), out, t, w, s));
     ADASAP_HIP(hipStreamSynchronize(s));
     return ADASAP_OK;
   }
