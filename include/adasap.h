@@ -145,6 +145,31 @@ adasap_status_t adasap_get_trace(adasap_handle_t h, double* eta, double* rho, do
 
 void adasap_destroy(adasap_handle_t h);
 
+/* One problem of a batch: X (device, n x d), Y (device, n x k), W (device, n x k: W_0 on
+ * entry, the solution on exit), all of the batch's dtype, and the problem's lengthscale. */
+typedef struct {
+  int64_t n;
+  int32_t d;
+  int32_t k;
+  const void* X;
+  const void* Y;
+  void* W;
+  double lengthscale;
+} adasap_problem_t;
+
+/* Solves `count` independent systems (K_p + lambda I) W_p = Y_p of uneven size together:
+ * every iteration advances all problems with batched launches (one persistent work-queue
+ * launch for all step-I kernel-block products).  The configuration is shared (kernel,
+ * lambda, block size b, rank, iterations, seed: problem p draws with seed + p); its
+ * lengthscale is replaced by each problem's own.  Requirements: FP32 precision, Nystrom
+ * preconditioner, accelerated steps with the gradient at Z, k = 1, 1 <= d <= 16 and n >= b
+ * for every problem.  When tol > 0 or check_every > 0 each problem's final relative residual
+ * is computed.  `reports` (host, count entries, may be NULL) receives per-problem statistics.
+ * Synchronises the stream. */
+adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int32_t count,
+                                   const adasap_config_t* cfg, int32_t dtype, void* stream,
+                                   adasap_report_t* reports);
+
 /* ---- single steps of the iteration, for parity checks of each step --------------- */
 
 /* Row block B_t of Alg. 2 Step I: a uniform b-subset of [0, n) without replacement,

@@ -45,6 +45,12 @@ class Config(ctypes.Structure):
     ]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("lengthscale", ctypes.c_double)]
+
+
 class Report(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int64), ("relres", ctypes.c_double), ("relres_maxcol", ctypes.c_double),
@@ -80,6 +86,8 @@ _SIGNATURES = {
     "adasap_kblock_matmul": (_I32, [_I32, _D, _I32, _I64, _I64, _I32, _I32, _P, _P, _P, _P, _I32, _P]),
     "adasap_nystrom": (_I32, [_I64, _I32, _P, _P, _D, _P, _P, _P, _P]),
     "adasap_precond_apply": (_I32, [_I64, _I32, _I32, _P, _P, _D, _I32, _P, _P, _P]),
+    "adasap_solve_batch": (_I32, [ctypes.POINTER(Problem), _I32, ctypes.POINTER(Config), _I32, _P,
+                                  ctypes.POINTER(Report)]),
     "adasap_last_error": (ctypes.c_char_p, []),
     "adasap_status_string": (ctypes.c_char_p, [_I32]),
 }
@@ -215,6 +223,26 @@ class Library:
                                                   _ptr(S), rho, power, _ptr(G2), _ptr(out),
                                                   _stream()))
         return out if G.dim() == 2 else out[:, 0]
+
+
+    def solve_batch(self, cfg, Xs, Ys, Ws, lengthscales):
+        """Solve len(Xs) independent problems together; W tensors are updated in place."""
+        P = len(Xs)
+        probs = (Problem * P)()
+        dtype = None
+        for p in range(P):
+            X, Y, W = Xs[p], Ys[p], Ws[p]
+            _check_dev(X, Y, W)
+            dtype = _dtype_code(X) if dtype is None else dtype
+            if _dtype_code(Y) != dtype or _dtype_code(W) != dtype or _dtype_code(X) != dtype:
+                raise TypeError("every array of a batch must have the same dtype")
+            probs[p].n, probs[p].d = X.shape[0], X.shape[1]
+            probs[p].k = 1 if Y.dim() == 1 else Y.shape[1]
+            probs[p].X, probs[p].Y, probs[p].W = X.data_ptr(), Y.data_ptr(), W.data_ptr()
+            probs[p].lengthscale = float(lengthscales[p])
+        reps = (Report * P)()
+        self.check(self.cdll.adasap_solve_batch(probs, P, ctypes.byref(cfg), dtype, _stream(), reps))
+        return [r.as_dict() for r in reps]
 
 
 class Handle:

@@ -24,6 +24,16 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// A batch of P independent problems of identical shapes.  Operand X of problem p starts at
+// X + p * sX elements; the launcher comments name which operand each stride belongs to.
+// The default (P = 1, zero strides) is a single problem.  Per-problem scalars live in
+// consecutive IterScalars entries (problem p uses sc + p).
+struct Batch {
+  int P = 1;
+  int64_t sA = 0, sB = 0, sC = 0, sD = 0, sE = 0;
+};
+constexpr int64_t SC_DOUBLES = sizeof(IterScalars) / sizeof(double);
+
 // ---- kernel-block products (kblock.hip) -------------------------------------------------
 // OUT[i, c] = sum_j k(Xr[ridx? ridx[i] : i], Xc[j]) R[j, c]  (+ epilogue, see KbEpilogue)
 // Xr, Xc element type xt; R element type rt (leading dimension ldr); accumulation in the
@@ -41,6 +51,8 @@ struct KbEpilogue {
   const int64_t* e2idx = nullptr;
   int64_t lde2 = 0;
   double a2 = 0.0;
+  // batches: problem p uses E1 + p*bsE1, E2 + p*bsE2 and index lists + p*bsIdx (elements)
+  int64_t bsE1 = 0, bsE2 = 0, bsIdx = 0;
 };
 
 adasap_status_t kblock_valu(int kern, double ell, int prec, int64_t m, int64_t n, int d, int k,
@@ -52,38 +64,41 @@ adasap_status_t kblock_valu(int kern, double ell, int prec, int64_t m, int64_t n
 // P = A^T B over rows [0, rows): A (rows x p, lda, type at), B (rows x q, ldb, type bt);
 // result p x q float64 row-major.  If rowscale != null row c of the result is multiplied by
 // rowscale[c].
+// Batch strides: sA (A), sB (B), sC (P), sD (rowscale).
 adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t lda, const void* B,
                      DT bt, int64_t ldb, double* P, const double* rowscale, DevBuf& part,
-                     hipStream_t s);
+                     hipStream_t s, const Batch& bt_ = Batch());
 
 // OUT (rows x q, ldo) = alpha_ptr? (*alpha_ptr) * E : 0  +  (A + (delta_ptr? *delta_ptr : 0) * A2) M
 // A, A2: rows x p float64 (lda); M: p x q float64 row-major; E: rows x q float64 (lde).
 // If alpha_sqrt_inv is set, the factor applied to E is 1/sqrt(*alpha_ptr) instead of 1/(*alpha_ptr);
 // alpha_mode: 0 => factor 1 (E added as is), 1 => 1/(*alpha), 2 => 1/sqrt(*alpha).
+// Batch strides: sA (A and A2), sB (M), sC (out), sD (E), sE (delta_ptr and alpha_ptr).
 adasap_status_t gemm_rm(int64_t rows, int p, int q, const double* A, const double* A2,
                         const double* delta_ptr, int64_t lda, const double* M, double* out,
                         int64_t ldo, const double* E, int64_t lde, const double* alpha_ptr,
-                        int alpha_mode, hipStream_t s);
+                        int alpha_mode, hipStream_t s, const Batch& bt = Batch());
 
 // Nystrom core (one workgroup): from Mo = Omega^T Ysk and Qo = Omega^T Omega (r x r),
 // Delta = eps * tr(Mo); C = sym(Mo) + Delta Qo = R^T R (retry Delta *= 10 up to 5 times);
 // writes Rinv = R^{-1} (r x r, upper) and scalars->delta / not_pd / failed.
+// Batched over P problems (r x r operands consecutive, sc + p).
 adasap_status_t nys_core(int r, const double* Mo, const double* Qo, double eps, double* Rinv,
-                         double* Rscratch, IterScalars* sc, hipStream_t s);
+                         double* Rscratch, IterScalars* sc, hipStream_t s, int P = 1);
 
 // Symmetric eigendecomposition of H (r x r, float64) by cyclic Jacobi with the
 // round-robin pairing.  Outputs eigenvalues evals (r, unsorted) and eigenvectors V
 // (r x r, columns).  rot_buf must hold jacobi_rot_capacity(r) doubles.
 size_t jacobi_rot_capacity(int r);
 adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, double* rot_buf,
-                           IterScalars* sc, hipStream_t s);
+                           IterScalars* sc, hipStream_t s, int P = 1);
 
 // Sort eigenpairs descending, S = max(0, sigma^2 - delta), rho (rule 0: lam + S[r-1],
 // rule 1: rho_fixed), T = V[:, perm] diag(1/sigma) (so that U = Bm T), and the Woodbury
 // coefficient vectors cinv = 1/(S+rho) - 1/rho, cisq = 1/sqrt(S+rho) - 1/sqrt(rho).
 adasap_status_t nys_finalize(int r, const double* evals, const double* V, int rho_rule,
                              double lam, double rho_fixed, double* S, double* T, double* cinv,
-                             double* cisq, IterScalars* sc, hipStream_t s);
+                             double* cisq, IterScalars* sc, hipStream_t s, int P = 1);
 
 // coefs = 1/(S+rho) - 1/rho (power 0) or 1/sqrt(S+rho) - 1/sqrt(rho) (power 1); sc->rho = rho
 adasap_status_t woodbury_coefs(int r, const double* S, double rho, int power, double* coefs,
@@ -91,18 +106,20 @@ adasap_status_t woodbury_coefs(int r, const double* S, double rho, int power, do
 
 // Vector helpers for randomized powering.
 // dots: sc->rq = v.z, sc->vnorm2 = z.z (float64, fixed-order reduction)
+// Batched over P problems with vectors b apart.
 adasap_status_t dots_vz(int64_t b, const double* v, const double* z, IterScalars* sc,
-                        DevBuf& part, hipStream_t s);
+                        DevBuf& part, hipStream_t s, int P = 1);
 // v = z / sqrt(sc->vnorm2); if last: sc->lam_hat = sc->rq, sc->eta = 1 / sc->rq
 adasap_status_t normalize_into(int64_t b, const double* z, double* v, IterScalars* sc, int last,
-                               hipStream_t s);
+                               hipStream_t s, int P = 1);
 // sc->vnorm2 = v.v then v /= sqrt(v.v)
 adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf& part,
-                                  hipStream_t s);
+                                  hipStream_t s, int P = 1);
 
 // ---- random numbers (rng.hip) -------------------------------------------------------------
+// Batched over P problems: problem p uses seed + p and writes out + p * count.
 adasap_status_t normals_dev(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
-                            double* out, hipStream_t s);
+                            double* out, hipStream_t s, int P = 1);
 void sample_block_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n, int64_t b,
                        int64_t* out);
 
@@ -119,16 +136,21 @@ struct NestCoef {
 };
 // Dense part on all rows (state type st): V' = beta V + (1-beta) Z, Z' = alpha*V(')+(1-alpha)Z;
 // if Wout: Wout = Z (old) before the update (type wt).
+// Batch: row_prob (per row) and coefs (beta, gamma, alpha per problem) select each row's constants.
 adasap_status_t nesterov_dense(int64_t count, void* V, void* Z, DT st, const NestCoef& c,
-                               void* Wout, DT wt, hipStream_t s);
+                               void* Wout, DT wt, hipStream_t s, const int32_t* row_prob = nullptr,
+                               const double* coefs = nullptr, int k = 1);
 // Sparse part on the b block rows: with eta = sc->eta,
 //  accel: V[B] -= gamma eta D;  Z[B] -= (alpha gamma + 1 - alpha) eta D  (z_uses_v_next)
 //                               Z[B] -= (1 - alpha) eta D                 (otherwise)
 //         Wout[B] -= eta D if Wout
 //  plain: Z[B] -= eta D (Z is the iterate W; V unused)
+// Batch: P problems, B and D of problem p at B + p*b, D + p*b*k (B holds global row indices),
+// scalars sc + p, constants coefs[3p..3p+2] when coefs is set.
 adasap_status_t nesterov_sparse(int64_t b, int k, const int64_t* B, const double* D, void* V,
                                 void* Z, DT st, const NestCoef& c, const IterScalars* sc,
-                                void* Wout, DT wt, hipStream_t s);
+                                void* Wout, DT wt, hipStream_t s, int P = 1,
+                                const double* coefs = nullptr);
 // a += b elementwise (a in place)
 adasap_status_t add_inplace(int64_t count, void* a, DT at, const void* b, DT bt, hipStream_t s);
 // acc += W (float64 accumulator, count elements) for tail averaging

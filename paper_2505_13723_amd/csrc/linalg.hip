@@ -16,6 +16,11 @@ __device__ inline double ld_any(const void* p, DT t, int64_t i) {
   return t == DT::F64 ? static_cast<const double*>(p)[i] : (double)static_cast<const float*>(p)[i];
 }
 
+// p advanced by e elements of type t
+__device__ inline const void* adv(const void* p, DT t, int64_t e) {
+  return static_cast<const char*>(p) + e * (t == DT::F64 ? 8 : 4);
+}
+
 // ---------------------------------------------------------------- Gram products P = A^T B
 constexpr int G_T = 16;      // output tile
 constexpr int G_ROWS = 32;   // rows staged per step
@@ -25,12 +30,17 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int p, 
                                                            const void* __restrict__ A, DT at,
                                                            int64_t lda, const void* __restrict__ B,
                                                            DT bt, int64_t ldb,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part, int nsplit,
+                                                           Batch bat) {
   __shared__ double As[G_ROWS][G_T];
   __shared__ double Bs[G_ROWS][G_T];
+  const int prob = blockIdx.z / nsplit, split = blockIdx.z % nsplit;
+  A = adv(A, at, prob * bat.sA);
+  B = adv(B, bt, prob * bat.sB);
+  part += (int64_t)prob * nsplit * p * q;
   const int tx = threadIdx.x % G_T, ty = threadIdx.x / G_T;
   const int pi = blockIdx.y * G_T + ty, qj = blockIdx.x * G_T + tx;
-  const int64_t r0 = (int64_t)blockIdx.z * G_CHUNK;
+  const int64_t r0 = (int64_t)split * G_CHUNK;
   const int64_t r1 = r0 + G_CHUNK < rows ? r0 + G_CHUNK : rows;
   double acc = 0.0;
   for (int64_t rr = r0; rr < r1; rr += G_ROWS) {
@@ -46,13 +56,18 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int p, 
     for (int l = 0; l < G_ROWS; ++l) acc += As[l][ty] * Bs[l][tx];
     __syncthreads();
   }
-  if (pi < p && qj < q) part[((int64_t)blockIdx.z * p + pi) * q + qj] = acc;
+  if (pi < p && qj < q) part[((int64_t)split * p + pi) * q + qj] = acc;
 }
 
 __global__ void gram_reduce_kernel(const double* __restrict__ part, int splits, int p, int q,
-                                   const double* __restrict__ rowscale, double* __restrict__ P) {
+                                   const double* __restrict__ rowscale, double* __restrict__ P,
+                                   Batch bat) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= p * q) return;
+  const int prob = blockIdx.y;
+  part += (int64_t)prob * splits * p * q;
+  P += prob * bat.sC;
+  if (rowscale) rowscale += prob * bat.sD;
   double s = 0.0;
   for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * p * q + e];
   if (rowscale) s *= rowscale[e / q];
@@ -66,8 +81,12 @@ __global__ __launch_bounds__(256) void gramv_partial_kernel(int64_t rows, int p,
                                                             const void* __restrict__ A, DT at,
                                                             int64_t lda, const void* __restrict__ B,
                                                             DT bt, int64_t ldb,
-                                                            double* __restrict__ part) {
+                                                            double* __restrict__ part, Batch bat) {
   __shared__ double red[128 * 4];
+  const int prob = blockIdx.y;
+  A = adv(A, at, prob * bat.sA);
+  B = adv(B, bt, prob * bat.sB);
+  part += (int64_t)prob * gridDim.x * p * q;
   const int col = threadIdx.x % 128, half = threadIdx.x / 128;
   const int64_t r0 = (int64_t)blockIdx.x * GV_CHUNK;
   const int64_t r1 = r0 + GV_CHUNK < rows ? r0 + GV_CHUNK : rows;
@@ -94,8 +113,14 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int
                                                         double* __restrict__ out, int64_t ldo,
                                                         const double* __restrict__ E, int64_t lde,
                                                         const double* __restrict__ alpha_ptr,
-                                                        int alpha_mode) {
+                                                        int alpha_mode, Batch bat) {
   __shared__ double Ms[128 * 4];
+  const int prob = blockIdx.y;
+  A += prob * bat.sA;
+  M += prob * bat.sB;
+  out += prob * bat.sC;
+  if (E) E += prob * bat.sD;
+  if (alpha_ptr) alpha_ptr += prob * bat.sE;
   for (int e = threadIdx.x; e < p * q; e += 256) Ms[e] = M[e];
   __syncthreads();
   const int lane = threadIdx.x % 64;
@@ -133,8 +158,16 @@ __global__ __launch_bounds__(256) void gemm_rm_kernel(int64_t rows, int p, int q
                                                       double* __restrict__ out, int64_t ldo,
                                                       const double* __restrict__ E, int64_t lde,
                                                       const double* __restrict__ alpha_ptr,
-                                                      int alpha_mode) {
+                                                      int alpha_mode, Batch bat) {
   __shared__ double As[M_T][M_T + 1];
+  const int prob = blockIdx.z;
+  A += prob * bat.sA;
+  if (A2) A2 += prob * bat.sA;
+  if (delta_ptr) delta_ptr += prob * bat.sE;
+  M += prob * bat.sB;
+  out += prob * bat.sC;
+  if (E) E += prob * bat.sD;
+  if (alpha_ptr) alpha_ptr += prob * bat.sE;
   __shared__ double Ms[M_T][M_T + 1];
   const int tc = threadIdx.x % M_T;
   const int tr = threadIdx.x / M_T;  // 0..7, rows tr*4 .. tr*4+3
@@ -185,6 +218,14 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
                                                         double* __restrict__ Rg,
                                                         IterScalars* __restrict__ sc) {
   __shared__ double C[RMAX * (RMAX + 1)];
+  {
+    const int64_t off = (int64_t)blockIdx.x * r * r;
+    Mo += off;
+    Qo += off;
+    Rinv += off;
+    if (Rg) Rg += off;
+    sc += blockIdx.x;
+  }
   __shared__ double xd[RMAX];
   __shared__ int flag;
   __shared__ double s_delta;
@@ -295,8 +336,13 @@ __device__ inline int rr_index(int i, int step, int rp) {
 __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __restrict__ Hg,
                                                       double* __restrict__ evals,
                                                       double* __restrict__ rot,
-                                                      IterScalars* __restrict__ sc) {
+                                                      IterScalars* __restrict__ sc,
+                                                      int64_t rot_cap) {
   __shared__ double H[RMAX * HS];
+  Hg += (int64_t)blockIdx.x * r * r;
+  evals += (int64_t)blockIdx.x * r;
+  rot += (int64_t)blockIdx.x * rot_cap;
+  sc += blockIdx.x;
   __shared__ double cs_c[RMAX / 2], cs_s[RMAX / 2];
   __shared__ int pp[RMAX / 2], qq[RMAX / 2];
   __shared__ int nrot;
@@ -386,7 +432,10 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
 constexpr int ACC_ROWS = 4;
 __global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
                                                            const IterScalars* __restrict__ sc,
-                                                           double* __restrict__ V) {
+                                                           double* __restrict__ V, int64_t rot_cap) {
+  rot += (int64_t)blockIdx.y * rot_cap;
+  sc += blockIdx.y;
+  V += (int64_t)blockIdx.y * r * r;
   __shared__ double Vs[ACC_ROWS][RMAX];
   __shared__ double R[(RMAX - 1) * (RMAX / 2) * 2];
   const int tid = threadIdx.x;
@@ -432,6 +481,16 @@ __global__ void nys_finalize_kernel(int r, const double* __restrict__ evals,
                                     double* __restrict__ T, double* __restrict__ cinv,
                                     double* __restrict__ cisq, IterScalars* __restrict__ sc) {
   __shared__ int perm[RMAX];
+  {
+    const int pb = blockIdx.x;
+    evals += (int64_t)pb * r;
+    V += (int64_t)pb * r * r;
+    S += (int64_t)pb * r;
+    T += (int64_t)pb * r * r;
+    cinv += (int64_t)pb * r;
+    cisq += (int64_t)pb * r;
+    sc += pb;
+  }
   __shared__ double sig2[RMAX];
   __shared__ double s_rho;
   const int i = threadIdx.x;
@@ -477,6 +536,9 @@ constexpr int DOT_PER_BLOCK = 4096;
 __global__ void dots_partial_kernel(int64_t n, const double* __restrict__ v,
                                     const double* __restrict__ z, double* __restrict__ part) {
   __shared__ double s1[DOT_BLOCK], s2[DOT_BLOCK];
+  v += (int64_t)blockIdx.y * n;
+  z += (int64_t)blockIdx.y * n;
+  part += (int64_t)blockIdx.y * 2 * gridDim.x;
   const int64_t base = (int64_t)blockIdx.x * DOT_PER_BLOCK;
   double a = 0.0, b = 0.0;
   for (int64_t i = base + threadIdx.x; i < base + DOT_PER_BLOCK && i < n; i += DOT_BLOCK) {
@@ -503,6 +565,8 @@ __global__ void dots_partial_kernel(int64_t n, const double* __restrict__ v,
 __global__ void dots_final_kernel(const double* __restrict__ part, int nblk,
                                   IterScalars* __restrict__ sc) {
   if (threadIdx.x != 0) return;
+  part += (int64_t)blockIdx.x * 2 * nblk;
+  sc += blockIdx.x;
   double a = 0.0, b = 0.0;
   for (int i = 0; i < nblk; ++i) {
     a += part[2 * i];
@@ -515,6 +579,9 @@ __global__ void dots_final_kernel(const double* __restrict__ part, int nblk,
 __global__ void normalize_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ v,
                                  IterScalars* __restrict__ sc, int last) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  z += (int64_t)blockIdx.y * n;
+  v += (int64_t)blockIdx.y * n;
+  sc += blockIdx.y;
   const double inv = 1.0 / sqrt(sc->vnorm2);
   if (i < n) v[i] = z[i] * inv;
   if (last && i == 0) {
@@ -542,32 +609,33 @@ adasap_status_t woodbury_coefs(int r, const double* S, double rho, int power, do
 
 adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t lda, const void* B,
                      DT bt, int64_t ldb, double* P, const double* rowscale, DevBuf& part,
-                     hipStream_t s) {
+                     hipStream_t s, const Batch& bat) {
+  const int NP = bat.P;
   if (q <= 4 && p <= 128) {
     int sp = (int)((rows + GV_CHUNK - 1) / GV_CHUNK);
     if (sp < 1) sp = 1;
-    ADASAP_TRY(part.ensure((size_t)sp * p * q * sizeof(double)));
+    ADASAP_TRY(part.ensure((size_t)NP * sp * p * q * sizeof(double)));
     if (rows > 0) {
-      hipLaunchKernelGGL(gramv_partial_kernel, dim3(sp), dim3(256), 0, s, rows, p, q, A, at, lda, B,
-                         bt, ldb, part.as<double>());
+      hipLaunchKernelGGL(gramv_partial_kernel, dim3(sp, NP), dim3(256), 0, s, rows, p, q, A, at, lda,
+                         B, bt, ldb, part.as<double>(), bat);
       ADASAP_LAUNCH_CHECK();
     } else {
-      ADASAP_HIP(hipMemsetAsync(part.p, 0, (size_t)p * q * sizeof(double), s));
+      ADASAP_HIP(hipMemsetAsync(part.p, 0, (size_t)NP * p * q * sizeof(double), s));
     }
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256), dim3(256), 0, s,
-                       part.as<double>(), sp, p, q, rowscale, P);
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256, NP), dim3(256), 0, s,
+                       part.as<double>(), sp, p, q, rowscale, P, bat);
     ADASAP_LAUNCH_CHECK();
     return ADASAP_OK;
   }
   int splits = (int)((rows + G_CHUNK - 1) / G_CHUNK);
   if (splits < 1) splits = 1;
-  ADASAP_TRY(part.ensure((size_t)splits * p * q * sizeof(double)));
-  const dim3 grid((q + G_T - 1) / G_T, (p + G_T - 1) / G_T, splits);
+  ADASAP_TRY(part.ensure((size_t)NP * splits * p * q * sizeof(double)));
+  const dim3 grid((q + G_T - 1) / G_T, (p + G_T - 1) / G_T, splits * NP);
   hipLaunchKernelGGL(gram_partial_kernel, grid, dim3(256), 0, s, rows, p, q, A, at, lda, B, bt,
-                     ldb, part.as<double>());
+                     ldb, part.as<double>(), splits, bat);
   ADASAP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256), dim3(256), 0, s,
-                     part.as<double>(), splits, p, q, rowscale, P);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256, NP), dim3(256), 0, s,
+                     part.as<double>(), splits, p, q, rowscale, P, bat);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
@@ -575,28 +643,28 @@ adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t l
 adasap_status_t gemm_rm(int64_t rows, int p, int q, const double* A, const double* A2,
                         const double* delta_ptr, int64_t lda, const double* M, double* out,
                         int64_t ldo, const double* E, int64_t lde, const double* alpha_ptr,
-                        int alpha_mode, hipStream_t s) {
+                        int alpha_mode, hipStream_t s, const Batch& bat) {
   if (rows <= 0) return ADASAP_OK;
   if (q <= 4 && p <= 128 && A2 == nullptr) {
-    hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, p,
-                       q, A, lda, M, out, ldo, E, lde, alpha_ptr, alpha_mode);
+    hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)((rows + 3) / 4), bat.P), dim3(256), 0, s,
+                       rows, p, q, A, lda, M, out, ldo, E, lde, alpha_ptr, alpha_mode, bat);
     ADASAP_LAUNCH_CHECK();
     return ADASAP_OK;
   }
-  const dim3 grid((q + M_T - 1) / M_T, (unsigned)((rows + M_T - 1) / M_T));
+  const dim3 grid((q + M_T - 1) / M_T, (unsigned)((rows + M_T - 1) / M_T), bat.P);
   hipLaunchKernelGGL(gemm_rm_kernel, grid, dim3(256), 0, s, rows, p, q, A, A2, delta_ptr, lda, M,
-                     out, ldo, E, lde, alpha_ptr, alpha_mode);
+                     out, ldo, E, lde, alpha_ptr, alpha_mode, bat);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
 
 adasap_status_t nys_core(int r, const double* Mo, const double* Qo, double eps, double* Rinv,
-                         double* Rscratch, IterScalars* sc, hipStream_t s) {
+                         double* Rscratch, IterScalars* sc, hipStream_t s, int P) {
   if (r < 1 || r > RMAX) {
     set_error("nys_core: rank must be in [1, 128]");
     return ADASAP_ERR_INVALID_ARG;
   }
-  hipLaunchKernelGGL(nys_core_kernel, dim3(1), dim3(1024), 0, s, r, Mo, Qo, eps, Rinv, Rscratch, sc);
+  hipLaunchKernelGGL(nys_core_kernel, dim3(P), dim3(1024), 0, s, r, Mo, Qo, eps, Rinv, Rscratch, sc);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
@@ -607,62 +675,62 @@ size_t jacobi_rot_capacity(int r) {
 }
 
 adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, double* rot_buf,
-                           IterScalars* sc, hipStream_t s) {
+                           IterScalars* sc, hipStream_t s, int P) {
   if (r < 1 || r > RMAX) {
     set_error("jacobi_eig: size must be in [1, 128]");
     return ADASAP_ERR_INVALID_ARG;
   }
   if (r == 1) {
     // 1 x 1: eigenvalue H, eigenvector 1
-    ADASAP_HIP(hipMemcpyAsync(evals, H, sizeof(double), hipMemcpyDeviceToDevice, s));
-    const double one = 1.0;
-    ADASAP_HIP(hipMemcpyAsync(V, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    std::vector<double> ones((size_t)P, 1.0);
+    ADASAP_HIP(hipMemcpyAsync(evals, H, sizeof(double) * P, hipMemcpyDeviceToDevice, s));
+    ADASAP_HIP(hipMemcpyAsync(V, ones.data(), sizeof(double) * P, hipMemcpyHostToDevice, s));
     ADASAP_HIP(hipStreamSynchronize(s));
     return ADASAP_OK;
   }
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, r, H, evals, rot_buf, sc);
+  const int64_t cap = (int64_t)jacobi_rot_capacity(r);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(P), dim3(1024), 0, s, r, H, evals, rot_buf, sc, cap);
   ADASAP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_ROWS - 1) / ACC_ROWS), dim3(256), 0, s, r,
-                     rot_buf, sc, V);
+  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_ROWS - 1) / ACC_ROWS, P), dim3(256), 0, s,
+                     r, rot_buf, sc, V, cap);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
 
 adasap_status_t nys_finalize(int r, const double* evals, const double* V, int rho_rule,
                              double lam, double rho_fixed, double* S, double* T, double* cinv,
-                             double* cisq, IterScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(nys_finalize_kernel, dim3(1), dim3(RMAX), 0, s, r, evals, V, rho_rule, lam,
+                             double* cisq, IterScalars* sc, hipStream_t s, int P) {
+  hipLaunchKernelGGL(nys_finalize_kernel, dim3(P), dim3(RMAX), 0, s, r, evals, V, rho_rule, lam,
                      rho_fixed, S, T, cinv, cisq, sc);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
 
 adasap_status_t dots_vz(int64_t b, const double* v, const double* z, IterScalars* sc,
-                        DevBuf& part, hipStream_t s) {
-  const int nblk = (int)((b + DOT_PER_BLOCK - 1) / DOT_PER_BLOCK);
-  ADASAP_TRY(part.ensure((size_t)2 * (nblk > 0 ? nblk : 1) * sizeof(double)));
-  if (nblk > 0) {
-    hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk), dim3(DOT_BLOCK), 0, s, b, v, z,
-                       part.as<double>());
-    ADASAP_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL(dots_final_kernel, dim3(1), dim3(64), 0, s, part.as<double>(), nblk, sc);
+                        DevBuf& part, hipStream_t s, int P) {
+  int nblk = (int)((b + DOT_PER_BLOCK - 1) / DOT_PER_BLOCK);
+  if (nblk < 1) nblk = 1;
+  ADASAP_TRY(part.ensure((size_t)2 * nblk * P * sizeof(double)));
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, P), dim3(DOT_BLOCK), 0, s, b, v, z,
+                     part.as<double>());
+  ADASAP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(dots_final_kernel, dim3(P), dim3(64), 0, s, part.as<double>(), nblk, sc);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
 
 adasap_status_t normalize_into(int64_t b, const double* z, double* v, IterScalars* sc, int last,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)((b + 255) / 256)), dim3(256), 0, s, b, z,
+                               hipStream_t s, int P) {
+  hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)((b + 255) / 256), P), dim3(256), 0, s, b, z,
                      v, sc, last);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
 
 adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf& part,
-                                  hipStream_t s) {
-  ADASAP_TRY(dots_vz(b, v, v, sc, part, s));
-  return normalize_into(b, v, v, sc, 0, s);
+                                  hipStream_t s, int P) {
+  ADASAP_TRY(dots_vz(b, v, v, sc, part, s, P));
+  return normalize_into(b, v, v, sc, 0, s, P);
 }
 
 }  // namespace adasap

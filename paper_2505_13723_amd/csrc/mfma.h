@@ -70,4 +70,42 @@ adasap_status_t mfma_product_rows(const MfmaPack& pk, const void* rowq, int64_t 
                                   DT rt, int k, int mode, void* out, DT ot, MfmaWork& w,
                                   hipStream_t s);
 
+// ---- batches of independent problems (all with two K-steps, d <= 16) --------------------------
+// Points of problem p occupy rows row_off[p] .. row_off[p] + ntiles[p]*32 of the global row
+// space (padding rows are zero); block indices passed to the batch launchers are global rows.
+struct MfmaBatchPack {
+  int P = 0;
+  int kern = 0;
+  std::vector<int64_t> n, ntiles, row_off, col_off;
+  std::vector<int> d;
+  int64_t rows_total = 0;
+  DevBuf rowv, cols, centre, flag, dvec, col_off_dev, rhs_off_dev;
+};
+
+// Work items (problem, row workgroup, column-tile chunk) of the persistent step-I launch.
+struct MfmaQueue {
+  int nitems = 0;
+  int rows_per_wg = 256;
+  DevBuf items, item_start, nchunk, counter;
+};
+
+adasap_status_t mfma_batch_pack_create(MfmaBatchPack& bp, int P, const int64_t* n, const int* d,
+                                       const void* const* X, DT xt, const double* ell, int kern,
+                                       hipStream_t s);
+// column fragments of every problem's block (B: P x b global row indices)
+adasap_status_t mfma_batch_pack_blocks(const MfmaBatchPack& bp, const int64_t* B, int64_t b,
+                                       DevBuf& colsB, hipStream_t s);
+// OUT[p] = K(X_B[p], X_B[p]) R[p] + epilogue for every problem (R, OUT: P x b x k float64)
+adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t* B, int64_t b,
+                                         const void* colsB, const double* R, int k, int mode,
+                                         double* out, const KbEpilogue& ep, MfmaWork& w,
+                                         hipStream_t s);
+adasap_status_t mfma_batch_queue_create(const MfmaBatchPack& bp, int64_t b, int64_t chunk_tiles,
+                                        MfmaQueue& q, hipStream_t s);
+// G[p] = K(X_B[p], X[p]) Z[p] + epilogue for all problems in one persistent launch
+// (Z: float32 on the global padded rows, k = 1)
+adasap_status_t mfma_batch_stepI(const MfmaBatchPack& bp, MfmaQueue& q, const int64_t* B, int64_t b,
+                                 const float* Z, double* out, const KbEpilogue& ep, MfmaWork& w,
+                                 hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 }  // namespace adasap

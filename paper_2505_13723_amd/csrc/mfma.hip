@@ -110,10 +110,14 @@ __global__ void rowpack_kernel(const void* __restrict__ X, DT xt, int64_t n, int
 // lane l holds column T*32 + cs*16 + l%16, entries ks*32 + 8(l/16) + 0..7.
 __global__ void colpack_kernel(const _Float16* __restrict__ rowv, const int64_t* __restrict__ idx,
                                int64_t cnt, int64_t ntiles, int d, int KS,
-                               half8* __restrict__ colA) {
+                               half8* __restrict__ colA, const int* __restrict__ dvec) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one fragment per thread
   const int64_t total = ntiles * 2 * KS * 64;
   if (e >= total) return;
+  // batch: problem blockIdx.y has its own index list, fragments and dimension
+  if (idx) idx += (int64_t)blockIdx.y * cnt;
+  colA += (int64_t)blockIdx.y * total;
+  if (dvec) d = dvec[blockIdx.y];
   const int lane = (int)(e % 64);
   const int ks = (int)((e / 64) % KS);
   const int cs = (int)((e / (64 * KS)) % 2);
@@ -145,6 +149,8 @@ __global__ __launch_bounds__(256) void colmax_partial_kernel(const void* __restr
                                                              int64_t rows, int k, int64_t ldr,
                                                              float* __restrict__ part) {
   __shared__ unsigned int mx[128];
+  R = static_cast<const char*>(R) + (int64_t)blockIdx.y * rows * ldr * (rt == DT::F64 ? 8 : 4);
+  part += (int64_t)blockIdx.y * gridDim.x * k;
   for (int c = threadIdx.x; c < k; c += 256) mx[c] = 0u;
   __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * 4096;
@@ -179,6 +185,8 @@ __global__ __launch_bounds__(256) void colmax_partial_kernel(const void* __restr
 // scale[c] = power of two with max|R[:, c]| / scale <= 2^14 (scale >= 2^-60), 1 if the column is 0
 __global__ void colmax_final_kernel(const float* __restrict__ part, int nblk, int k,
                                     float* __restrict__ scale) {
+  part += (int64_t)blockIdx.x * nblk * k;
+  scale += (int64_t)blockIdx.x * k;
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     float m = 0.0f;
     for (int b = 0; b < nblk; ++b) m = fmaxf(m, part[(int64_t)b * k + c]);
@@ -211,6 +219,9 @@ __global__ void rhspack16_kernel(const void* __restrict__ R, DT rt, int64_t rows
   const int q = (int)((e / 64) % NQ);
   const int64_t T = e / (64 * NQ);
   const int rhs = q * 16 + lane % 16;
+  R = static_cast<const char*>(R) + (int64_t)blockIdx.y * rows * ldr * (rt == DT::F64 ? 8 : 4);
+  scale += (int64_t)blockIdx.y * k;
+  out += (int64_t)blockIdx.y * ntiles * NQ * parts * 64;
   half8 hi, lo;
   const float inv = rhs < k ? 1.0f / scale[rhs] : 0.0f;
   for (int m = 0; m < 8; ++m) {
@@ -238,6 +249,8 @@ __global__ void rhspack32_kernel(const void* __restrict__ R, DT rt, int64_t rows
                                  float* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= npad * KC) return;
+  R = static_cast<const char*>(R) + (int64_t)blockIdx.y * rows * ldr * (rt == DT::F64 ? 8 : 4);
+  out += (int64_t)blockIdx.y * npad * KC;
   const int64_t i = e / KC;
   const int c = (int)(e % KC);
   float v = 0.0f;
@@ -265,6 +278,11 @@ __device__ inline float kval(float s, float p) {
   }
 }
 
+struct MkItem {
+  int prob, rw;     // problem and row workgroup
+  int64_t T0, T1;   // column tiles [T0, T1) of that problem
+};
+
 struct MkArgs {
   const half8* colA;     // column fragments [ntiles][2][KS][64]
   const half8* rowv;     // row vectors [points][8] (64 float16 each)
@@ -279,47 +297,50 @@ struct MkArgs {
   float* part;           // [splits][m][k]
   int k;
   float p;               // Matern factor
+  // batches of equal-shape problems (blockIdx.y = problem): per-problem strides
+  int64_t bs_colA;       // half8
+  int64_t bs_ridx;       // indices
+  int64_t bs_rhs;        // bytes
+  int64_t bs_part;       // floats
+  // work-queue launches over problems of uneven size
+  const MkItem* items;
+  int nitems;
+  int* counter;
+  const int64_t* colA_off;  // per problem, half8
+  const int64_t* rhs_off;   // per problem, bytes
 };
 
 template <int MODE, int NQ>
 constexpr int mk_occupancy() { return 2; }
 
-template <int KS, int KERN, int MODE, int NQ, int RT>
-__global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkArgs a) {
-  // LDS: two buffers of (column fragments, right-hand-side fragments)
-  constexpr int A_FR = 2 * KS * 64;                                            // half8 per tile
-  constexpr int R_FR = MODE == MODE_F16 ? NQ * 64 : (MODE == MODE_F16X3 ? 2 * NQ * 64 : 0);
-  constexpr int R_F32 = MODE == MODE_F32V ? TILE * NQ : 0;                     // floats (NQ = KC)
-  constexpr int TOTAL16 = A_FR + R_FR + (R_F32 * 4) / 16;  // 16-byte words of one tile
-  constexpr int BUF_BYTES = ((TOTAL16 + 255) / 256) * 256 * 16;  // padded to whole load rounds
-  __shared__ __attribute__((aligned(16))) char lds[2 * BUF_BYTES];
+template <int KS, int MODE, int NQ>
+struct MkShape {
+  static constexpr int A_FR = 2 * KS * 64;                                            // half8 per tile
+  static constexpr int R_FR = MODE == MODE_F16 ? NQ * 64 : (MODE == MODE_F16X3 ? 2 * NQ * 64 : 0);
+  static constexpr int R_F32 = MODE == MODE_F32V ? TILE * NQ : 0;                     // floats (NQ = KC)
+  static constexpr int TOTAL16 = A_FR + R_FR + (R_F32 * 4) / 16;  // 16-byte words of one tile
+  static constexpr int BUF_BYTES = ((TOTAL16 + 255) / 256) * 256 * 16;  // whole load rounds
+};
 
+// Streams column tiles [T0, T1) of one problem against the rows of row workgroup rw and
+// writes the partial sums of rows row_base.. to out[(row - out_row0) * k + c].
+template <int KS, int KERN, int MODE, int NQ, int RT>
+__device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const void* rhs_p,
+                         const int64_t* ridx, int rw, int64_t T0, int64_t T1, float* out,
+                         int64_t out_row0) {
+  using SH = MkShape<KS, MODE, NQ>;
+  constexpr int A_FR = SH::A_FR, R_FR = SH::R_FR, R_F32 = SH::R_F32, TOTAL16 = SH::TOTAL16;
+  constexpr int BUF_BYTES = SH::BUF_BYTES;
   const int tid = threadIdx.x;
   const int lane = tid % 64;
   const int wave = tid / 64;
-  const int bid = blockIdx.x;
-  int split, rw;
-  if (a.xcd_map) {
-    // workgroups are dealt round-robin to the 8 XCDs: keep every row workgroup of one column
-    // split on the same XCD so they share the split's column stream in that XCD's L2
-    const int xcd = bid % 8, local = bid / 8;
-    split = xcd + 8 * (local / a.rwg);
-    rw = local % a.rwg;
-  } else {
-    split = bid / a.rwg;
-    rw = bid % a.rwg;
-  }
-  const int64_t T0 = (int64_t)split * a.tiles_per_split;
-  int64_t T1 = T0 + a.tiles_per_split;
-  if (T1 > a.ntiles) T1 = a.ntiles;
   const int64_t row_base = ((int64_t)rw * WAVES + wave) * RT * 16;
-
   // row operands (constant over the column stream)
   half8 Bfr[RT][KS];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int64_t row = row_base + rt * 16 + lane % 16;
-    const int64_t pt = row < a.m ? (a.ridx ? a.ridx[row] : row) : (a.ridx ? a.ridx[0] : 0);
+    const int64_t pt = row < a.m ? (ridx ? ridx[row] : row) : (ridx ? ridx[0] : 0);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) Bfr[rt][ks] = a.rowv[pt * 8 + ks * 4 + lane / 16];
   }
@@ -348,8 +369,8 @@ __global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkA
   // branch-free loads (one basic block, so the wait before each LDS store covers exactly the
   // older of the two register stages); lanes past the tile's data read a valid dummy address
   auto gload = [&](uint4 (&st)[LOADS16], int64_t T) {
-    const uint4* ca = reinterpret_cast<const uint4*>(a.colA) + T * A_FR;
-    const uint4* rb = reinterpret_cast<const uint4*>(a.rhs) + T * (R_FR + (R_F32 * 4) / 16);
+    const uint4* ca = reinterpret_cast<const uint4*>(colA_p) + T * A_FR;
+    const uint4* rb = reinterpret_cast<const uint4*>(rhs_p) + T * (R_FR + (R_F32 * 4) / 16);
 #pragma unroll
     for (int u = 0; u < LOADS16; ++u) {
       const int e = tid + u * 256;
@@ -440,7 +461,6 @@ __global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkA
   }
 
   // write partial sums
-  float* part = a.part + (int64_t)split * a.m * a.k;
   if constexpr (MODE == MODE_F32V) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -450,7 +470,7 @@ __global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkA
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
         const int64_t row = row_base + rt * 16 + lane % 16;
-        if (lane < 16 && row < a.m && c < a.k) part[row * a.k + c] = v;
+        if (lane < 16 && row < a.m && c < a.k) out[(row - out_row0) * a.k + c] = v;
       }
     }
   } else {
@@ -463,9 +483,57 @@ __global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkA
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int rhs = q * 16 + 4 * (lane / 16) + j;
-          if (rhs < a.k) part[row * a.k + rhs] = acc[rt][q][j];
+          if (rhs < a.k) out[(row - out_row0) * a.k + rhs] = acc[rt][q][j];
         }
     }
+  }
+}
+
+template <int KS, int KERN, int MODE, int NQ, int RT>
+__global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkArgs a) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * MkShape<KS, MODE, NQ>::BUF_BYTES];
+  const int bid = blockIdx.x;
+  const int prob = blockIdx.y;
+  int split, rw;
+  if (a.xcd_map) {
+    // workgroups are dealt round-robin to the 8 XCDs: keep every row workgroup of one column
+    // split on the same XCD so they share the split's column stream in that XCD's L2
+    const int xcd = bid % 8, local = bid / 8;
+    split = xcd + 8 * (local / a.rwg);
+    rw = local % a.rwg;
+  } else {
+    split = bid / a.rwg;
+    rw = bid % a.rwg;
+  }
+  const int64_t T0 = (int64_t)split * a.tiles_per_split;
+  int64_t T1 = T0 + a.tiles_per_split;
+  if (T1 > a.ntiles) T1 = a.ntiles;
+  mk_tiles<KS, KERN, MODE, NQ, RT>(
+      a, lds, a.colA + prob * a.bs_colA, static_cast<const char*>(a.rhs) + prob * a.bs_rhs,
+      a.ridx ? a.ridx + prob * a.bs_ridx : nullptr, rw, T0, T1,
+      a.part + prob * a.bs_part + (int64_t)split * a.m * a.k, 0);
+}
+
+// Persistent work-queue form for a batch of problems with uneven column counts: each
+// workgroup takes (problem, row workgroup, tile range) items from a global counter until the
+// table is exhausted; item i writes its partial sums to part[i][rows of its workgroup][k].
+template <int KS, int KERN, int MODE, int NQ, int RT>
+__global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mkq_kernel(MkArgs a) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * MkShape<KS, MODE, NQ>::BUF_BYTES];
+  __shared__ int s_item;
+  constexpr int ROWS = WAVES * RT * 16;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= a.nitems) break;
+    const MkItem it = a.items[item];
+    mk_tiles<KS, KERN, MODE, NQ, RT>(
+        a, lds, a.colA + a.colA_off[it.prob],
+        static_cast<const char*>(a.rhs) + a.rhs_off[it.prob],
+        a.ridx + (int64_t)it.prob * a.bs_ridx, it.rw, it.T0, it.T1,
+        a.part + (int64_t)item * ROWS * a.k, (int64_t)it.rw * ROWS);
   }
 }
 
@@ -475,6 +543,17 @@ __global__ void mk_reduce_kernel(const float* __restrict__ part, int splits, int
                                  void* __restrict__ out, DT ot) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * k) return;
+  {
+    // batch: problem blockIdx.y
+    const int64_t pb = blockIdx.y;
+    part += pb * splits * m * k;
+    if (scale) scale += pb * k;
+    out = static_cast<char*>(out) + pb * m * k * (ot == DT::F64 ? 8 : 4);
+    if (ep.E1) ep.E1 = static_cast<const char*>(ep.E1) + pb * ep.bsE1 * (ep.e1t == DT::F64 ? 8 : 4);
+    if (ep.E2) ep.E2 = static_cast<const char*>(ep.E2) + pb * ep.bsE2 * (ep.e2t == DT::F64 ? 8 : 4);
+    if (ep.e1idx) ep.e1idx += pb * ep.bsIdx;
+    if (ep.e2idx) ep.e2idx += pb * ep.bsIdx;
+  }
   const int64_t i = e / k;
   const int c = (int)(e % k);
   double s = 0.0;
@@ -533,6 +612,31 @@ adasap_status_t disp_kern(const MkArgs& a, int kern, int mode, int nq, int grid,
   }
 }
 
+template <int KS, int KERN, int MODE, int NQ, int RT>
+void launch_mk_grid(const MkArgs& a, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((mk_kernel<KS, KERN, MODE, NQ, RT>), grid, dim3(256), 0, s, a);
+}
+
+template <int KS, int KERN>
+void disp_mode_grid(const MkArgs& a, int mode, int nq, dim3 grid, hipStream_t s) {
+  if (mode == MODE_F32V) {
+    if (nq == 1) launch_mk_grid<KS, KERN, MODE_F32V, 1, 4>(a, grid, s);
+    else if (nq == 2) launch_mk_grid<KS, KERN, MODE_F32V, 2, 4>(a, grid, s);
+    else launch_mk_grid<KS, KERN, MODE_F32V, 4, 4>(a, grid, s);
+  } else if (mode == MODE_F16X3) {
+    switch (nq) {
+      case 1: launch_mk_grid<KS, KERN, MODE_F16X3, 1, 4>(a, grid, s); break;
+      case 2: launch_mk_grid<KS, KERN, MODE_F16X3, 2, 4>(a, grid, s); break;
+      case 3: launch_mk_grid<KS, KERN, MODE_F16X3, 3, 4>(a, grid, s); break;
+      case 4: launch_mk_grid<KS, KERN, MODE_F16X3, 4, 4>(a, grid, s); break;
+      case 5: launch_mk_grid<KS, KERN, MODE_F16X3, 5, 2>(a, grid, s); break;
+      case 6: launch_mk_grid<KS, KERN, MODE_F16X3, 6, 2>(a, grid, s); break;
+      case 7: launch_mk_grid<KS, KERN, MODE_F16X3, 7, 2>(a, grid, s); break;
+      default: launch_mk_grid<KS, KERN, MODE_F16X3, 8, 2>(a, grid, s); break;
+    }
+  }
+}
+
 inline int ksteps(int d) { return 3 * d + 6 <= 32 ? 1 : 2; }
 
 double sigma_for(int kern, double ell) {
@@ -554,7 +658,7 @@ struct RhsDesc {
 adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
                        const int64_t* ridx, int64_t m, int d, int kern, const RhsDesc& rd, int k,
                        void* out, DT ot, const KbEpilogue& ep, DevBuf& part, hipStream_t s,
-                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int ks_force = 0) {
   if (m <= 0) return ADASAP_OK;
   const int RT = (rd.mode != MODE_F32V && rd.nq > 4) ? 2 : 4;
   const int rows_per_wg = WAVES * RT * 16;
@@ -570,7 +674,7 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
   if (splits < 1) splits = 1;
   const int xcd_map = (splits % 8 == 0) ? 1 : 0;
   ADASAP_TRY(part.ensure((size_t)splits * m * k * sizeof(float)));
-  MkArgs a;
+  MkArgs a{};
   a.colA = colA;
   a.rowv = rowv;
   a.ridx = ridx;
@@ -585,7 +689,7 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
   a.k = k;
   a.p = matern_factor(kern);
   const int grid = rwg * splits;
-  const int KS = ksteps(d);
+  const int KS = ks_force ? ks_force : ksteps(d);
   if (ev0) ADASAP_HIP(hipEventRecord(ev0, s));
   if (KS == 1) ADASAP_TRY(disp_kern<1>(a, kern, rd.mode, rd.nq, grid, s));
   else ADASAP_TRY(disp_kern<2>(a, kern, rd.mode, rd.nq, grid, s));
@@ -652,6 +756,33 @@ adasap_status_t pack_rhs(const void* R, DT rt, int64_t rows, int k, int64_t ldr,
 
 }  // namespace
 
+// ---------------------------------------------------------------- batches
+// step-I partial sums of the work-queue items back to G[p][i][c] (+ epilogue)
+__global__ void mkq_reduce_kernel(const float* __restrict__ part, const int64_t* __restrict__ item_start,
+                                  const int* __restrict__ nchunk, int64_t b, int k, int rows_per_wg,
+                                  KbEpilogue ep, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b * k) return;
+  const int pb = blockIdx.y;
+  const int64_t i = e / k;
+  const int c = (int)(e % k);
+  const int rw = (int)(i / rows_per_wg);
+  const int nc = nchunk[pb];
+  const int64_t first = item_start[pb] + (int64_t)rw * nc;
+  double s = 0.0;
+  for (int j = 0; j < nc; ++j) s += (double)part[((first + j) * rows_per_wg + (i - (int64_t)rw * rows_per_wg)) * k + c];
+  auto ld = [](const void* p, DT t, int64_t j) {
+    return t == DT::F64 ? static_cast<const double*>(p)[j] : (double)static_cast<const float*>(p)[j];
+  };
+  const int64_t* i1 = ep.e1idx ? ep.e1idx + (int64_t)pb * ep.bsIdx : nullptr;
+  const int64_t* i2 = ep.e2idx ? ep.e2idx + (int64_t)pb * ep.bsIdx : nullptr;
+  if (ep.E1) s += ep.a1 * ld(ep.E1, ep.e1t, (i1 ? i1[i] : i) * ep.lde1 + c);
+  if (ep.E2) s += ep.a2 * ld(ep.E2, ep.e2t, (i2 ? i2[i] : i) * ep.lde2 + c);
+  out[(int64_t)pb * b * k + e] = s;
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
 // ---------------------------------------------------------------- public launchers
 size_t mfma_pack_bytes(int64_t n, int d, int k) {
   const int64_t nt = (n + TILE - 1) / TILE;
@@ -693,7 +824,8 @@ adasap_status_t mfma_pack_create(MfmaPack& pk, int64_t n, int d, int k, const vo
   ADASAP_LAUNCH_CHECK();
   const int64_t nfr = pk.ntiles * 2 * KS * 64;
   hipLaunchKernelGGL(colpack_kernel, dim3((unsigned)((nfr + 255) / 256)), dim3(256), 0, s,
-                     pk.rowv.as<_Float16>(), nullptr, n, pk.ntiles, d, KS, pk.cols.as<half8>());
+                     pk.rowv.as<_Float16>(), nullptr, n, pk.ntiles, d, KS, pk.cols.as<half8>(),
+                     nullptr);
   ADASAP_LAUNCH_CHECK();
   int flag = 0;
   ADASAP_HIP(hipMemcpyAsync(&flag, pk.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -713,7 +845,7 @@ adasap_status_t mfma_pack_block(const MfmaPack& pk, const int64_t* B, int64_t b,
   ADASAP_TRY(colsB.ensure((size_t)nt * 2 * KS * 64 * 16));
   const int64_t nfr = nt * 2 * KS * 64;
   hipLaunchKernelGGL(colpack_kernel, dim3((unsigned)((nfr + 255) / 256)), dim3(256), 0, s,
-                     pk.rowv.as<_Float16>(), B, b, nt, pk.d, KS, colsB.as<half8>());
+                     pk.rowv.as<_Float16>(), B, b, nt, pk.d, KS, colsB.as<half8>(), nullptr);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
@@ -779,6 +911,266 @@ adasap_status_t mfma_product_rows(const MfmaPack& pk, const void* rowq, int64_t 
   KbEpilogue none;
   return mk_run(pk.cols.as<half8>(), pk.ntiles, static_cast<const half8*>(rowq), nullptr, m, pk.d,
                 pk.kern, rd, k, out, ot, none, w.part, s);
+}
+
+adasap_status_t mfma_batch_pack_create(MfmaBatchPack& bp, int P, const int64_t* n, const int* d,
+                                       const void* const* X, DT xt, const double* ell, int kern,
+                                       hipStream_t s) {
+  bp.P = P;
+  bp.kern = kern;
+  bp.n.assign(n, n + P);
+  bp.d.assign(d, d + P);
+  bp.ntiles.resize(P);
+  bp.row_off.resize(P);
+  bp.col_off.resize(P);
+  int64_t rows = 0, cols = 0;
+  for (int p = 0; p < P; ++p) {
+    if (d[p] < 1 || d[p] > 16) {
+      set_error("batched solves need 1 <= d <= 16 for every problem");
+      return ADASAP_ERR_INVALID_ARG;
+    }
+    bp.ntiles[p] = (n[p] + TILE - 1) / TILE;
+    bp.row_off[p] = rows;
+    bp.col_off[p] = cols;
+    rows += bp.ntiles[p] * TILE;
+    cols += bp.ntiles[p] * 2 * 2 * 64;  // two K-steps for every batched problem
+  }
+  bp.rows_total = rows;
+  ADASAP_TRY(bp.rowv.ensure((size_t)rows * ROWVEC * 2));
+  ADASAP_TRY(bp.cols.ensure((size_t)cols * 16));
+  ADASAP_TRY(bp.flag.ensure(sizeof(int)));
+  ADASAP_TRY(bp.centre.ensure((size_t)16 * sizeof(double)));
+  ADASAP_TRY(bp.dvec.ensure((size_t)P * sizeof(int)));
+  ADASAP_TRY(bp.col_off_dev.ensure((size_t)P * sizeof(int64_t)));
+  ADASAP_TRY(bp.rhs_off_dev.ensure((size_t)P * sizeof(int64_t)));
+  ADASAP_HIP(hipMemcpyAsync(bp.dvec.p, d, (size_t)P * sizeof(int), hipMemcpyHostToDevice, s));
+  ADASAP_HIP(hipMemcpyAsync(bp.col_off_dev.p, bp.col_off.data(), (size_t)P * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+  std::vector<int64_t> rhs_off(P);
+  for (int p = 0; p < P; ++p) rhs_off[p] = bp.row_off[p] * (int64_t)sizeof(float);  // k = 1 float32
+  ADASAP_HIP(hipMemcpyAsync(bp.rhs_off_dev.p, rhs_off.data(), (size_t)P * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+  ADASAP_HIP(hipMemsetAsync(bp.flag.p, 0, sizeof(int), s));
+  DevBuf tmp;
+  for (int p = 0; p < P; ++p) {
+    const int nblk = (int)((n[p] + 4095) / 4096);
+    ADASAP_TRY(tmp.ensure((size_t)nblk * d[p] * sizeof(double)));
+    hipLaunchKernelGGL(mean_partial_kernel, dim3(nblk), dim3(64), 0, s, X[p], xt, n[p], d[p],
+                       tmp.as<double>());
+    hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64), 0, s, tmp.as<double>(), nblk, d[p],
+                       n[p], bp.centre.as<double>());
+    const int64_t npad = bp.ntiles[p] * TILE;
+    _Float16* rv = bp.rowv.as<_Float16>() + bp.row_off[p] * ROWVEC;
+    hipLaunchKernelGGL(rowpack_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, X[p],
+                       xt, n[p], npad, d[p], bp.centre.as<double>(), sigma_for(kern, ell[p]), rv,
+                       bp.flag.as<int>());
+    const int64_t nfr = bp.ntiles[p] * 2 * 2 * 64;
+    hipLaunchKernelGGL(colpack_kernel, dim3((unsigned)((nfr + 255) / 256)), dim3(256), 0, s, rv,
+                       nullptr, n[p], bp.ntiles[p], d[p], 2, bp.cols.as<half8>() + bp.col_off[p],
+                       nullptr);
+    ADASAP_LAUNCH_CHECK();
+    ADASAP_HIP(hipStreamSynchronize(s));  // the centre buffer is reused by the next problem
+  }
+  int flag = 0;
+  ADASAP_HIP(hipMemcpy(&flag, bp.flag.p, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    set_error("scaled coordinates exceed the float16 range of the matrix-core path");
+    return ADASAP_ERR_UNSUPPORTED;
+  }
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_batch_pack_blocks(const MfmaBatchPack& bp, const int64_t* B, int64_t b,
+                                       DevBuf& colsB, hipStream_t s) {
+  const int64_t nt = (b + TILE - 1) / TILE;
+  const int64_t nfr = nt * 2 * 2 * 64;
+  ADASAP_TRY(colsB.ensure((size_t)bp.P * nfr * 16));
+  hipLaunchKernelGGL(colpack_kernel, dim3((unsigned)((nfr + 255) / 256), bp.P), dim3(256), 0, s,
+                     bp.rowv.as<_Float16>(), B, b, nt, 0, 2, colsB.as<half8>(), bp.dvec.as<int>());
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t* B, int64_t b,
+                                         const void* colsB, const double* R, int k, int mode,
+                                         double* out, const KbEpilogue& ep, MfmaWork& w,
+                                         hipStream_t s) {
+  const int P = bp.P;
+  const int64_t nt = (b + TILE - 1) / TILE;
+  RhsDesc rd;
+  rd.mode = mode;
+  if (mode == MODE_F32V) {
+    const int kc = k == 1 ? 1 : (k == 2 ? 2 : 4);
+    const int64_t npad = nt * TILE;
+    ADASAP_TRY(w.rhs.ensure((size_t)P * npad * kc * sizeof(float)));
+    const int64_t tot = npad * kc;
+    const dim3 g((unsigned)((tot + 255) / 256), P);
+    if (kc == 1) hipLaunchKernelGGL(rhspack32_kernel<1>, g, dim3(256), 0, s, R, DT::F64, b, k, k, nullptr, npad, w.rhs.as<float>());
+    else if (kc == 2) hipLaunchKernelGGL(rhspack32_kernel<2>, g, dim3(256), 0, s, R, DT::F64, b, k, k, nullptr, npad, w.rhs.as<float>());
+    else hipLaunchKernelGGL(rhspack32_kernel<4>, g, dim3(256), 0, s, R, DT::F64, b, k, k, nullptr, npad, w.rhs.as<float>());
+    ADASAP_LAUNCH_CHECK();
+    rd.nq = kc;
+    rd.p = w.rhs.p;
+    rd.scale = nullptr;
+  } else {
+    const int nq = (k + 15) / 16;
+    const int parts = mode == MODE_F16X3 ? 2 : 1;
+    ADASAP_TRY(w.rhs.ensure((size_t)P * nt * nq * parts * 64 * 16));
+    ADASAP_TRY(w.scale.ensure((size_t)P * k * sizeof(float)));
+    const int nblk = (int)((b + 4095) / 4096);
+    ADASAP_TRY(w.tmp.ensure((size_t)P * nblk * k * sizeof(float)));
+    hipLaunchKernelGGL(colmax_partial_kernel, dim3(nblk, P), dim3(256), 0, s, R, DT::F64, b, k, k,
+                       w.tmp.as<float>());
+    hipLaunchKernelGGL(colmax_final_kernel, dim3(P), dim3(128), 0, s, w.tmp.as<float>(), nblk, k,
+                       w.scale.as<float>());
+    const int64_t tot = nt * nq * 64;
+    hipLaunchKernelGGL(rhspack16_kernel, dim3((unsigned)((tot + 255) / 256), P), dim3(256), 0, s, R,
+                       DT::F64, b, k, k, nullptr, w.scale.as<float>(), nt, nq, parts,
+                       w.rhs.as<half8>());
+    ADASAP_LAUNCH_CHECK();
+    rd.nq = nq;
+    rd.p = w.rhs.p;
+    rd.scale = w.scale.as<float>();
+  }
+  const int RT = (rd.mode != MODE_F32V && rd.nq > 4) ? 2 : 4;
+  const int rows_per_wg = WAVES * RT * 16;
+  const int rwg = (int)((b + rows_per_wg - 1) / rows_per_wg);
+  int splits = (int)((2048 / P + rwg - 1) / rwg);
+  if (splits > nt) splits = (int)nt;
+  if (splits < 1) splits = 1;
+  int64_t tps = (nt + splits - 1) / splits;
+  splits = (int)((nt + tps - 1) / tps);
+  ADASAP_TRY(w.part.ensure((size_t)P * splits * b * k * sizeof(float)));
+  MkArgs a{};
+  a.colA = static_cast<const half8*>(colsB);
+  a.rowv = bp.rowv.as<half8>();
+  a.ridx = B;
+  a.m = b;
+  a.rhs = rd.p;
+  a.ntiles = nt;
+  a.tiles_per_split = tps;
+  a.splits = splits;
+  a.rwg = rwg;
+  a.xcd_map = 0;
+  a.part = w.part.as<float>();
+  a.k = k;
+  a.p = matern_factor(bp.kern);
+  a.bs_colA = nt * 2 * 2 * 64;
+  a.bs_ridx = b;
+  if (mode == MODE_F32V) a.bs_rhs = nt * TILE * rd.nq * (int64_t)sizeof(float);
+  else a.bs_rhs = nt * rd.nq * (mode == MODE_F16X3 ? 2 : 1) * 64 * 16;
+  a.bs_part = (int64_t)splits * b * k;
+  const dim3 grid(rwg * splits, P);
+  switch (bp.kern) {
+    case ADASAP_RBF: disp_mode_grid<2, ADASAP_RBF>(a, rd.mode, rd.nq, grid, s); break;
+    case ADASAP_MATERN12: disp_mode_grid<2, ADASAP_MATERN12>(a, rd.mode, rd.nq, grid, s); break;
+    case ADASAP_MATERN32: disp_mode_grid<2, ADASAP_MATERN32>(a, rd.mode, rd.nq, grid, s); break;
+    default: disp_mode_grid<2, ADASAP_MATERN52>(a, rd.mode, rd.nq, grid, s); break;
+  }
+  ADASAP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(mk_reduce_kernel, dim3((unsigned)((b * k + 255) / 256), P), dim3(256), 0, s,
+                     w.part.as<float>(), splits, b, k, rd.scale, ep, out, DT::F64);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_batch_queue_create(const MfmaBatchPack& bp, int64_t b, int64_t chunk_tiles,
+                                        MfmaQueue& q, hipStream_t s) {
+  const int P = bp.P;
+  const int rows_per_wg = WAVES * 4 * 16;
+  const int rwg = (int)((b + rows_per_wg - 1) / rows_per_wg);
+  std::vector<MkItem> items;
+  std::vector<int64_t> start(P);
+  std::vector<int> nch(P);
+  for (int p = 0; p < P; ++p) {
+    const int64_t nt = bp.ntiles[p];
+    const int nc = (int)((nt + chunk_tiles - 1) / chunk_tiles);
+    start[p] = (int64_t)items.size();
+    nch[p] = nc;
+    for (int rw = 0; rw < rwg; ++rw)
+      for (int c = 0; c < nc; ++c) {
+        MkItem it;
+        it.prob = p;
+        it.rw = rw;
+        it.T0 = (int64_t)c * chunk_tiles;
+        it.T1 = it.T0 + chunk_tiles < nt ? it.T0 + chunk_tiles : nt;
+        items.push_back(it);
+      }
+  }
+  q.nitems = (int)items.size();
+  q.rows_per_wg = rows_per_wg;
+  ADASAP_TRY(q.items.ensure(items.size() * sizeof(MkItem)));
+  ADASAP_TRY(q.item_start.ensure((size_t)P * sizeof(int64_t)));
+  ADASAP_TRY(q.nchunk.ensure((size_t)P * sizeof(int)));
+  ADASAP_TRY(q.counter.ensure(sizeof(int)));
+  ADASAP_HIP(hipMemcpyAsync(q.items.p, items.data(), items.size() * sizeof(MkItem),
+                            hipMemcpyHostToDevice, s));
+  ADASAP_HIP(hipMemcpyAsync(q.item_start.p, start.data(), (size_t)P * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+  ADASAP_HIP(hipMemcpyAsync(q.nchunk.p, nch.data(), (size_t)P * sizeof(int), hipMemcpyHostToDevice, s));
+  ADASAP_HIP(hipStreamSynchronize(s));
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_batch_stepI(const MfmaBatchPack& bp, MfmaQueue& q, const int64_t* B, int64_t b,
+                                 const float* Z, double* out, const KbEpilogue& ep, MfmaWork& w,
+                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  ADASAP_TRY(w.part.ensure((size_t)q.nitems * q.rows_per_wg * sizeof(float)));
+  MkArgs a{};
+  a.colA = bp.cols.as<half8>();
+  a.rowv = bp.rowv.as<half8>();
+  a.ridx = B;
+  a.m = b;
+  a.rhs = Z;
+  a.k = 1;
+  a.p = matern_factor(bp.kern);
+  a.part = w.part.as<float>();
+  a.bs_ridx = b;
+  a.items = q.items.as<MkItem>();
+  a.nitems = q.nitems;
+  a.counter = q.counter.as<int>();
+  a.colA_off = bp.col_off_dev.as<int64_t>();
+  a.rhs_off = bp.rhs_off_dev.as<int64_t>();
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, a.counter);
+  ADASAP_LAUNCH_CHECK();
+  int dev = 0, cus = 256;
+  ADASAP_HIP(hipGetDevice(&dev));
+  ADASAP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int grid = cus * 2;  // two workgroups per CU, each drains the queue
+  if (ev0) ADASAP_HIP(hipEventRecord(ev0, s));
+  switch (bp.kern) {
+    case ADASAP_RBF: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_RBF, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    case ADASAP_MATERN12: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN12, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    case ADASAP_MATERN32: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN32, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN52, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
+  }
+  ADASAP_LAUNCH_CHECK();
+  if (ev1) ADASAP_HIP(hipEventRecord(ev1, s));
+  hipLaunchKernelGGL(mkq_reduce_kernel, dim3((unsigned)((b + 255) / 256), bp.P), dim3(256), 0, s,
+                     w.part.as<float>(), q.item_start.as<int64_t>(), q.nchunk.as<int>(), b, 1,
+                     q.rows_per_wg, ep, out);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t mfma_batch_residual(const MfmaBatchPack& bp, int p, const void* W, DT wt,
+                                    const void* Y, DT yt, double lam, double* res, MfmaWork& w,
+                                    hipStream_t s) {
+  RhsDesc rd;
+  ADASAP_TRY(pack_rhs(W, wt, bp.n[p], 1, 1, nullptr, bp.ntiles[p], MODE_F16X3, w.rhs, w.scale,
+                      w.tmp, rd, s));
+  KbEpilogue ep;
+  ep.E1 = W;
+  ep.e1t = wt;
+  ep.lde1 = 1;
+  ep.a1 = lam;
+  ep.E2 = Y;
+  ep.e2t = yt;
+  ep.lde2 = 1;
+  ep.a2 = -1.0;
+  return mk_run(bp.cols.as<half8>() + bp.col_off[p], bp.ntiles[p],
+                bp.rowv.as<half8>() + bp.row_off[p] * 8, nullptr, bp.n[p], bp.d[p], bp.kern, rd, 1,
+                res, DT::F64, ep, w.part, s, nullptr, nullptr, 2);
 }
 
 int mfma_mode_f16() { return MODE_F16; }

@@ -17,6 +17,8 @@ namespace {
 __global__ void normals_kernel(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
                                double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  seed += blockIdx.y;  // problem p of a batch draws with seed + p
+  out += (int64_t)blockIdx.y * count;
   if (2 * i >= count) return;
   const u64x4 w = philox4x64_10((uint64_t)i + 1, t, 0, 0, seed, purpose);
   const double two_pi = 6.283185307179586;
@@ -63,10 +65,10 @@ uint64_t bounded(HostStream& hs, uint64_t s) {
 }  // namespace
 
 adasap_status_t normals_dev(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
-                            double* out, hipStream_t s) {
+                            double* out, hipStream_t s, int P) {
   if (count <= 0) return ADASAP_OK;
   const int64_t blocks = (count + 1) / 2;
-  hipLaunchKernelGGL(normals_kernel, dim3((unsigned)((blocks + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(normals_kernel, dim3((unsigned)((blocks + 255) / 256), P), dim3(256), 0, s,
                      seed, purpose, t, count, out);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;

@@ -52,9 +52,16 @@ __global__ void convert_kernel(int64_t count, const void* __restrict__ src, DT s
 template <typename T>
 __global__ void nesterov_dense_kernel(int64_t count, T* __restrict__ V, T* __restrict__ Z,
                                       double beta, double alpha, int z_next, void* __restrict__ W,
-                                      DT wt) {
+                                      DT wt, const int32_t* __restrict__ row_prob,
+                                      const double* __restrict__ coefs, int k) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
+  if (row_prob) {
+    // batch: (beta, gamma, alpha) of the problem owning this row
+    const int pb = row_prob[i / k];
+    beta = coefs[3 * pb];
+    alpha = coefs[3 * pb + 2];
+  }
   const double v = (double)V[i], z = (double)Z[i];
   if (W) st_dt(W, wt, i, z);
   const double vn = beta * v + (1.0 - beta) * z;
@@ -68,9 +75,19 @@ __global__ void nesterov_sparse_kernel(int64_t b, int k, const int64_t* __restri
                                        const double* __restrict__ D, T* __restrict__ V,
                                        T* __restrict__ Z, double gamma, double alpha, int accel,
                                        int z_next, const IterScalars* __restrict__ sc,
-                                       void* __restrict__ W, DT wt) {
+                                       void* __restrict__ W, DT wt,
+                                       const double* __restrict__ coefs) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= b * k) return;
+  // batch: problem blockIdx.y has its block, direction and scalars b*k apart
+  const int pb = blockIdx.y;
+  B += (int64_t)pb * b;
+  D += (int64_t)pb * b * k;
+  sc += pb;
+  if (coefs) {
+    gamma = coefs[3 * pb + 1];
+    alpha = coefs[3 * pb + 2];
+  }
   const int64_t i = e / k;
   const int c = (int)(e % k);
   const int64_t g = B[i] * k + c;
@@ -133,33 +150,34 @@ adasap_status_t convert(int64_t count, const void* src, DT st, void* dst, DT dt,
 }
 
 adasap_status_t nesterov_dense(int64_t count, void* V, void* Z, DT st, const NestCoef& c,
-                               void* Wout, DT wt, hipStream_t s) {
+                               void* Wout, DT wt, hipStream_t s, const int32_t* row_prob,
+                               const double* coefs, int k) {
   if (count <= 0) return ADASAP_OK;
   if (st == DT::F64)
     hipLaunchKernelGGL(nesterov_dense_kernel<double>, dim3(nblocks(count)), dim3(256), 0, s, count,
                        static_cast<double*>(V), static_cast<double*>(Z), c.beta, c.alpha,
-                       c.z_uses_v_next, Wout, wt);
+                       c.z_uses_v_next, Wout, wt, row_prob, coefs, k);
   else
     hipLaunchKernelGGL(nesterov_dense_kernel<float>, dim3(nblocks(count)), dim3(256), 0, s, count,
                        static_cast<float*>(V), static_cast<float*>(Z), c.beta, c.alpha,
-                       c.z_uses_v_next, Wout, wt);
+                       c.z_uses_v_next, Wout, wt, row_prob, coefs, k);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
 
 adasap_status_t nesterov_sparse(int64_t b, int k, const int64_t* B, const double* D, void* V,
                                 void* Z, DT st, const NestCoef& c, const IterScalars* sc,
-                                void* Wout, DT wt, hipStream_t s) {
+                                void* Wout, DT wt, hipStream_t s, int P, const double* coefs) {
   const int64_t count = b * k;
   if (count <= 0) return ADASAP_OK;
   if (st == DT::F64)
-    hipLaunchKernelGGL(nesterov_sparse_kernel<double>, dim3(nblocks(count)), dim3(256), 0, s, b, k,
-                       B, D, static_cast<double*>(V), static_cast<double*>(Z), c.gamma, c.alpha,
-                       c.accel, c.z_uses_v_next, sc, Wout, wt);
+    hipLaunchKernelGGL(nesterov_sparse_kernel<double>, dim3(nblocks(count), P), dim3(256), 0, s, b,
+                       k, B, D, static_cast<double*>(V), static_cast<double*>(Z), c.gamma, c.alpha,
+                       c.accel, c.z_uses_v_next, sc, Wout, wt, coefs);
   else
-    hipLaunchKernelGGL(nesterov_sparse_kernel<float>, dim3(nblocks(count)), dim3(256), 0, s, b, k,
-                       B, D, static_cast<float*>(V), static_cast<float*>(Z), c.gamma, c.alpha,
-                       c.accel, c.z_uses_v_next, sc, Wout, wt);
+    hipLaunchKernelGGL(nesterov_sparse_kernel<float>, dim3(nblocks(count), P), dim3(256), 0, s, b,
+                       k, B, D, static_cast<float*>(V), static_cast<float*>(Z), c.gamma, c.alpha,
+                       c.accel, c.z_uses_v_next, sc, Wout, wt, coefs);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
