@@ -13,7 +13,13 @@ time to relative residual 1e-3 (iterations timed on the device, residual checks
 once per data pass off the clock), the roofline of the dominant kernel, and the
 CPU float64 oracle timed on a bounded sample on the host.
 
+With --workload batched it instead times the 256-problem batch (n_p log-uniform in
+[2000, 65536], d_p in {4..16}, ell_p ~ U(0.2, 2), lambda = 1e-2, b = 1024, r = 64, FP32):
+a step is one round, one ADASAP iteration of every problem with one persistent Step-I
+launch; `value` is the batch's aggregate kernel-block GFLOP/s.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-ttr] [--no-cpu]
+                       [--workload c3|batched]
 """
 import argparse
 import json
@@ -29,6 +35,8 @@ if ROOT not in sys.path:
 METRIC = "time to rel. residual 1e-3 (s) & kernel-block GFLOP/s, n=2M d=11, 1 GPU"
 # published MI355X peaks used for the roofline fraction
 PEAK_F16_MFMA_TFLOPS = 2500.0
+# transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 8 lanes per clock x 2.4 GHz
+PEAK_EXP_TPS = 256 * 4 * 8 * 2.4e9 / 1e12
 
 
 def log(msg):
@@ -45,6 +53,7 @@ def main():
     ap.add_argument("--ttr-passes", type=int, default=40, help="data passes allowed for time-to-residual")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=384)
+    ap.add_argument("--workload", choices=["c3", "batched"], default="c3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -54,6 +63,8 @@ def main():
     import torch
     from paper_2505_13723_amd import binding, inputs
 
+    if args.workload == "batched":
+        return bench_batched(args, torch, binding, inputs)
     cfgw = dict(inputs.WORKLOADS["c3_rbf_n2m_k64"])
     n, d, k = args.n, cfgw["d"], cfgw["k"]
     b, r, lam, ell = cfgw["b"], cfgw["r"], cfgw["lam"], cfgw["ell"]
@@ -135,6 +146,93 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_batched(args, torch, binding, inputs):
+    """256 independent uneven problems, one round = one iteration of each."""
+    import numpy as np
+
+    w = inputs.WORKLOADS["c4_batched_256"]
+    ns, ds, ells = inputs.c4_problem_sizes(seed=w["seed"], count=w["count"], nmin=w["nmin"],
+                                           nmax=w["nmax"], dmin=w["dmin"], dmax=w["dmax"],
+                                           ellmin=w["ellmin"], ellmax=w["ellmax"])
+    b, r, lam = w["b"], w["r"], w["lam"]
+    lib = binding.load()
+    log("generating %d problems, %d rows in total" % (len(ns), int(ns.sum())))
+    Xs, Ys, Ws, host = [], [], [], []
+    for p in range(len(ns)):
+        X, y = inputs.make_c4_problem(p, int(ns[p]), int(ds[p]), seed=w["seed"])
+        if p < 8:
+            host.append((X, y))
+        Xs.append(torch.as_tensor(X, dtype=torch.float32).cuda())
+        Ys.append(torch.as_tensor(y[:, None], dtype=torch.float32).cuda())
+        Ws.append(torch.zeros((int(ns[p]), 1), dtype=torch.float32, device="cuda"))
+
+    def run(iters):
+        cfg = lib.config(kernel="rbf", lam=lam, block_size=b, rank=r, max_iters=iters,
+                         seed=w["seed"], precision="fp32")
+        for W in Ws:
+            W.zero_()
+        torch.cuda.synchronize()
+        return lib.solve_batch(cfg, Xs, Ys, Ws, ells)
+
+    if args.warmup > 0:
+        run(args.warmup)
+    t0 = time.perf_counter()
+    reps = run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rep = reps[0]
+    ms_per_step = rep["solve_ms"] / max(1, rep["iters"])
+    pairs = float(b) * float(ns.sum())
+    flops = float(b) * float(np.sum(ns * (2 * ds + 2)))
+    value = flops / (ms_per_step * 1e-3) / 1e9
+    kern_ms = rep["step1_kernel_ms"] / max(1, rep["step1_launches"])
+    achieved = pairs / (kern_ms * 1e-3) / 1e12
+    log("rounds=%d solve_ms=%.2f (%.3f ms/round), wall %.3f s, step-I kernel %.3f ms"
+        % (rep["iters"], rep["solve_ms"], ms_per_step, wall, kern_ms))
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_batched(host, ds, ells, b)
+        log("cpu baseline: %s" % json.dumps(cpu))
+    line = {
+        "metric": "batched kernel-block GFLOP/s, 256 uneven problems, 1 GPU", "value": round(value, 1),
+        "unit": "GFLOP/s", "n_gpus": 1, "steps": rep["iters"], "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (f16 hi/lo matrix-core distances), f64 Nystrom cores",
+        "data": "synthetic (seeded Gaussian X, sum-of-sines targets)",
+        "config": {"workload": "batched_256_rbf_uneven", "problems": len(ns), "rows": int(ns.sum()),
+                   "b": b, "r": r, "lambda": lam, "kernel": "rbf", "precision": "fp32"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
+                     "unit": "Texp/s", "frac": round(achieved / PEAK_EXP_TPS, 4), "traffic": None,
+                     "kernel": "mkq_kernel (persistent batched Step-I product)",
+                     "kernel_ms": round(kern_ms, 4), "algorithmic_exp_per_launch": pairs},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_batched(host, ds, ells, b):
+    """The float64 oracle's Step-I product for the first problems of the batch (one thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import kernels as OK
+    from oracle import rng as OR
+
+    flops, sec = 0.0, 0.0
+    with threadpool_limits(limits=1):
+        for p, (X, y) in enumerate(host):
+            B = OR.sample_block(4 + p, 0, X.shape[0], b)
+            t0 = time.perf_counter()
+            OK.kernel_matmul(X[B], X, y[:, None], OK.RBF, float(ells[p]))
+            sec += time.perf_counter() - t0
+            flops += float(b) * X.shape[0] * (2 * int(ds[p]) + 2)
+            if sec > 20:
+                break
+    return {"value": round(flops / sec / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "Step-I products of the first %d problems (b=%d rows against all n_p "
+                      "columns, float64 numpy, one thread): %.2f s" % (p + 1, b, sec)}
 
 
 def cpu_baseline(X, Y, rows, ell, d, k, b, n):

@@ -138,6 +138,15 @@ adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, cons
 adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres,
                                 double* relres_maxcol);
 
+/* The block gradient of Step I of Alg. 2 at a caller-given point:
+ * G = K(X_B, X) Z + lambda Z[B] - Y[B], where B = B_t is the block adasap_solve samples at
+ * iteration t (sorted, from the handle's seed), computed with the same kernels, precision
+ * and launch as the solver's own Step I.  Z (device, n x k, handle dtype) is read only;
+ * G_out (device, b x k, float64) and, if non-NULL, B_out (device, b int64) are written.
+ * Returns after the stream completes. */
+adasap_status_t adasap_block_gradient(adasap_handle_t h, int64_t t, const void* Z, int64_t* B_out,
+                                      double* G_out);
+
 /* Per-iteration step sizes eta_t, dampings rho_t and Rayleigh quotients of the last
  * solve, copied to host arrays of length `count` (entries beyond the run are left). */
 adasap_status_t adasap_get_trace(adasap_handle_t h, double* eta, double* rho, double* lambda_hat,

@@ -80,6 +80,7 @@ _SIGNATURES = {
     "adasap_predict": (_I32, [_P, _P, _I64, _P, _P]),
     "adasap_residual": (_I32, [_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "adasap_get_trace": (_I32, [_P, _P, _P, _P, _I64]),
+    "adasap_block_gradient": (_I32, [_P, _I64, _P, _P, _P]),
     "adasap_destroy": (None, [_P]),
     "adasap_sample_block": (_I32, [_U64, _U64, _U64, _I64, _I64, _P]),
     "adasap_normals": (_I32, [_U64, _U64, _U64, _I64, _P, _P]),
@@ -268,6 +269,16 @@ class Handle:
         a, m = ctypes.c_double(), ctypes.c_double()
         self.lib.check(self.lib.cdll.adasap_residual(self.h, _ptr(W), ctypes.byref(a), ctypes.byref(m)))
         return a.value, m.value
+
+    def block_gradient(self, t, Z):
+        """(B_t, G) of Step I at iterate Z, through the solver's own Step-I launch."""
+        torch = _torch()
+        _check_dev(Z)
+        b = self.cfg.block_size
+        B = torch.empty(b, dtype=torch.int64, device=self.X.device)
+        G = torch.empty((b, self.Y.shape[1]), dtype=torch.float64, device=self.X.device)
+        self.lib.check(self.lib.cdll.adasap_block_gradient(self.h, int(t), _ptr(Z), _ptr(B), _ptr(G)))
+        return B, G
 
     def trace(self, count):
         eta, rho, lh = (np.full(count, np.nan) for _ in range(3))

@@ -162,6 +162,35 @@ adasap_status_t precond_apply_h(adasap_handle_t h, int kk, const double* Xin, do
                  Xin, kk, &sc->rho, power == 0 ? 1 : 2, st);
 }
 
+// Step I product G = K(X_B, X) Zc + lambda Zc[B] - rhs[B] (b x k, float64), with the
+// launch the solver uses: matrix cores for the reduced precisions (float16 products for
+// MIXED, float16 hi/lo or float32-vector products for FP32), vector ALUs otherwise
+adasap_status_t block_gradient_h(adasap_handle_t h, const int64_t* B, const void* gp, DT gt,
+                                 const void* rhs, DT rhst, double* G, hipStream_t s) {
+  const adasap_config_t& c = h->cfg;
+  const int64_t n = h->n, b = c.block_size;
+  const int k = h->k;
+  KbEpilogue epg;
+  epg.E1 = gp;
+  epg.e1t = gt;
+  epg.e1idx = B;
+  epg.lde1 = k;
+  epg.a1 = c.lambda;
+  epg.E2 = rhs;
+  epg.e2t = rhst;
+  epg.e2idx = B;
+  epg.lde2 = k;
+  epg.a2 = -1.0;
+  if (h->use_mfma) {
+    const int mode = c.precision == ADASAP_MIXED ? mfma_mode_f16()
+                                                 : (k <= 4 ? mfma_mode_f32v() : mfma_mode_f16x3());
+    return mfma_product(h->pack, B, b, nullptr, 0, gp, gt, k, mode, G, DT::F64, epg, h->mw, s);
+  }
+  const int kprec = c.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
+  return hk_kblock(h, b, n, h->X, B, h->dtype, h->X, gp, gt, k, k, G, DT::F64, k, epg, kprec, s,
+                   h->part_kb);
+}
+
 // one ADASAP iteration; rhs is the current right-hand side (Y or a refinement residual)
 adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* rhs, DT rhst,
                         void* Wout) {
@@ -192,19 +221,7 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   const bool at_w = c.accel && !c.grad_at_z;
   const void* gp = at_w ? Wout : h->Z.p;
   const DT gt = at_w ? h->dtype : h->st;
-  KbEpilogue epg;
-  epg.E1 = gp;
-  epg.e1t = gt;
-  epg.e1idx = B;
-  epg.lde1 = k;
-  epg.a1 = c.lambda;
-  epg.E2 = rhs;
-  epg.e2t = rhst;
-  epg.e2idx = B;
-  epg.lde2 = k;
-  epg.a2 = -1.0;
   if (h->use_mfma) {
-    const int mode = prec == ADASAP_MIXED ? mfma_mode_f16() : (k <= 4 ? mfma_mode_f32v() : mfma_mode_f16x3());
     if ((int64_t)h->kev.size() < 2 * (h->kev_used + 1)) {
       for (int e = 0; e < 2; ++e) {
         hipEvent_t ev;
@@ -215,14 +232,12 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
     h->mw.ev0 = h->kev[2 * h->kev_used];
     h->mw.ev1 = h->kev[2 * h->kev_used + 1];
     ++h->kev_used;
-    const adasap_status_t pst = mfma_product(h->pack, B, b, nullptr, 0, gp, gt, k, mode, h->G.p,
-                                             DT::F64, epg, h->mw, s);
+    const adasap_status_t pst = block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s);
     h->mw.ev0 = h->mw.ev1 = nullptr;
     ADASAP_TRY(pst);
     ADASAP_TRY(mfma_pack_block(h->pack, B, b, h->colsB, s2));
   } else {
-    ADASAP_TRY(hk_kblock(h, b, n, h->X, B, h->dtype, h->X, gp, gt, k, k, h->G.p, DT::F64, k,
-                         epg, kprec, s, h->part_kb));
+    ADASAP_TRY(block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s));
   }
 
   const bool nys = c.precond == ADASAP_PRECOND_NYSTROM;
@@ -677,6 +692,24 @@ adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres
   if (!h) return invalid("handle is null");
   if (!W) return invalid("W must be a non-null device pointer");
   return residual_h(h, W, h->dtype, h->Y, h->dtype, relres, relres_maxcol, false);
+}
+
+adasap_status_t adasap_block_gradient(adasap_handle_t h, int64_t t, const void* Z, int64_t* B_out,
+                                      double* G_out) {
+  if (!h) return invalid("handle is null");
+  if (t < 0) return invalid("t must be >= 0");
+  if (!Z || !G_out) return invalid("Z and G_out must be non-null device pointers");
+  const int64_t b = h->cfg.block_size;
+  ADASAP_HIP(hipEventSynchronize(h->bev[0]));
+  sample_block_host(h->cfg.seed, PURPOSE_B, (uint64_t)t, h->n, b, h->Bhost[0]);
+  ADASAP_HIP(hipMemcpyAsync(h->Bdev.p, h->Bhost[0], b * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
+  ADASAP_HIP(hipEventRecord(h->bev[0], h->s));
+  const int64_t* B = h->Bdev.as<int64_t>();
+  ADASAP_TRY(block_gradient_h(h, B, Z, h->dtype, h->Y, h->dtype, G_out, h->s));
+  if (B_out)
+    ADASAP_HIP(hipMemcpyAsync(B_out, B, b * sizeof(int64_t), hipMemcpyDeviceToDevice, h->s));
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  return ADASAP_OK;
 }
 
 adasap_status_t adasap_get_trace(adasap_handle_t h, double* eta, double* rho, double* lambda_hat,
