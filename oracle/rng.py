@@ -21,6 +21,8 @@ from one published generator so that they can be compared:
   word 2e + 1.
 * Bounded integer in [0, s): Lemire's multiply-shift with rejection
   ("Fast random integer generation in an interval", 2019).
+* Permutation of [0, m): Fisher-Yates from the top, element i swapped with a
+  bounded integer in [0, i + 1) (Durstenfeld, CACM 1964).
 * Block B: Floyd's algorithm for a uniform b-subset of [0, n) without
   replacement (Bentley & Floyd, CACM 1987), sorted ascending (reading of
   the paper's "uniform" block distribution: without replacement, independent
@@ -38,6 +40,8 @@ PHILOX_W1 = 0xBB67AE8584CAA73B
 PURPOSE_B = 5
 PURPOSE_OMEGA = 6
 PURPOSE_POW = 7
+# minibatch order of the warm-start network's training, epoch e = counter t
+PURPOSE_MINIBATCH = 11
 # refinement sweep s draws with purpose + PURPOSE_SWEEP_STRIDE * s
 PURPOSE_SWEEP_STRIDE = 16
 
@@ -171,3 +175,14 @@ def sample_block(seed, t, n, b, purpose=PURPOSE_B):
         v = bounded(ws, j + 1)
         chosen.add(j if v in chosen else v)
     return np.array(sorted(chosen), dtype=np.int64)
+
+
+def permutation(seed, purpose, t, m):
+    """Uniform permutation of [0, m): Fisher-Yates, i = m-1 down to 1, swap i with
+    bounded(i + 1)."""
+    ws = WordStream(seed, purpose, t)
+    perm = np.arange(m, dtype=np.int64)
+    for i in range(m - 1, 0, -1):
+        j = bounded(ws, i + 1)
+        perm[i], perm[j] = perm[j], perm[i]
+    return perm

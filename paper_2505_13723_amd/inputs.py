@@ -35,6 +35,11 @@ WORKLOADS = {
     # learned warm start target problem
     "c5_rbf_n100m": dict(n=100_000_000, d=9, kernel="rbf", ell=0.1, lam=1e-2, b=32768, r=128,
                          rho_rule=0, k=1, precision="fp32", seed=5),
+    # warm-start training windows and target drawn from one field at the point density of
+    # 1e8 points in the unit cube (d = 9, RBF ell = 0.1); network D = 512 cosines,
+    # three hidden layers of 256
+    "ws_rbf_d9": dict(d=9, ell=0.1, density=1e8, field_features=5000, D=512, H=256,
+                      windows=32, n_window=8192, n_target=65536, b=4096, r=128, seed=6),
 }
 
 
@@ -163,3 +168,59 @@ def make_small(seed, n, d, k=1, dist="normal", noise=0.1):
     X = rs.standard_normal((n, d)) if dist == "normal" else rs.uniform(0, 1, (n, d))
     Y = np.sin(X).sum(axis=1, keepdims=True) + noise * rs.standard_normal((n, k))
     return X, Y
+
+
+def box_side(n, density, d):
+    """Side of the cube that holds n points at the given density."""
+    return (n / density) ** (1.0 / d)
+
+
+def ws_field(seed, d, ell, features=5000):
+    """One RBF prior draw f(x) = sqrt(2/F) sum_j theta_j cos(omega_j . x + c_j), as
+    (frequencies F x d, phases F, theta F)."""
+    rs = np.random.default_rng(seed)
+    Wf, c = rff_frequencies(rs, "rbf", ell, d, features)
+    return Wf, c, rs.standard_normal(features)
+
+
+def ws_points(field, n, lo, side, noise_var, seed, device="cpu", chunk=1 << 15):
+    """n points uniform in the cube [lo, lo + side]^d and y = f(x) + N(0, noise_var),
+    as float64 torch tensors on `device`."""
+    torch = _torch()
+    Wf, c, theta = field
+    rs = np.random.default_rng(seed)
+    d = Wf.shape[1]
+    X = torch.as_tensor(np.asarray(lo) + side * rs.uniform(0.0, 1.0, (n, d)), device=device)
+    Wt = torch.as_tensor(Wf, device=device)
+    ct = torch.as_tensor(c, device=device)
+    th = torch.as_tensor(theta, device=device)
+    y = torch.empty(n, dtype=torch.float64, device=device)
+    for i0 in range(0, n, chunk):
+        y[i0:i0 + chunk] = torch.cos(X[i0:i0 + chunk] @ Wt.T + ct) @ th
+    y *= math.sqrt(2.0 / Wf.shape[0])
+    y += math.sqrt(noise_var) * torch.as_tensor(rs.standard_normal(n), device=device)
+    return X, y
+
+
+def ws_window_corners(seed, count, d, outer, side):
+    """Lower corners of `count` windows of the given side inside [0, outer]^d."""
+    rs = np.random.default_rng(seed)
+    return rs.uniform(0.0, max(0.0, outer - side), (count, d))
+
+
+def ws_rff(seed, d, ell, D):
+    """The network's D cosine frequencies (N(0, ell^-2 I)) and phases (U[0, 2 pi))."""
+    return rff_frequencies(np.random.default_rng(seed), "rbf", ell, d, D)
+
+
+def ws_init_params(seed, sizes):
+    """Flat initial parameters of the dense layers sizes[0] -> ... -> sizes[-1]: weights
+    uniform with variance 1/fan_in, biases zero; layer order W_l (out x in), b_l."""
+    rs = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(sizes) - 1):
+        fan_in, fan_out = sizes[i], sizes[i + 1]
+        a = math.sqrt(3.0 / fan_in)
+        parts.append(rs.uniform(-a, a, fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts)
