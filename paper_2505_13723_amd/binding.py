@@ -1,4 +1,5 @@
-"""Thin ctypes binding of libadasap.so (the C ABI declared in include/adasap.h).
+"""Thin ctypes binding of libadasap.so (the C ABI declared in include/adasap.h and
+include/adasap_warm.h).
 
 Only argument marshalling lives here: torch tensors are passed as device pointers
 with torch's current HIP stream; every step of the computation runs in the
@@ -66,6 +67,12 @@ class Report(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class WsConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("d", ctypes.c_int32), ("D", ctypes.c_int32),
+                ("hidden", ctypes.c_int32), ("lam", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("adam_eps", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
@@ -89,6 +96,19 @@ _SIGNATURES = {
     "adasap_precond_apply": (_I32, [_I64, _I32, _I32, _P, _P, _D, _I32, _P, _P, _P]),
     "adasap_solve_batch": (_I32, [ctypes.POINTER(Problem), _I32, ctypes.POINTER(Config), _I32, _P,
                                   ctypes.POINTER(Report)]),
+    "adasap_ws_config_default": (_I32, [ctypes.POINTER(WsConfig)]),
+    "adasap_ws_param_count": (_I64, [ctypes.POINTER(WsConfig)]),
+    "adasap_ws_create": (_I32, [ctypes.POINTER(WsConfig), _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "adasap_ws_add_problem": (_I32, [_P, _I64, _P, _P, _P]),
+    "adasap_ws_train_rows": (_I64, [_P]),
+    "adasap_ws_train": (_I32, [_P, _I32, _I32, _D, _U64, _P]),
+    "adasap_ws_features": (_I32, [_P, _I64, _P, _P, _P, _P]),
+    "adasap_ws_loss_grad": (_I32, [_P, _I64, _P, _P, ctypes.POINTER(_D), _P]),
+    "adasap_ws_predict_mean": (_I32, [_P, _I64, _P, _P, _P]),
+    "adasap_ws_initial_iterate": (_I32, [_P, _I64, _P, _P, _P]),
+    "adasap_ws_get_params": (_I32, [_P, _P]),
+    "adasap_ws_set_params": (_I32, [_P, _P]),
+    "adasap_ws_destroy": (None, [_P]),
     "adasap_last_error": (ctypes.c_char_p, []),
     "adasap_status_string": (ctypes.c_char_p, [_I32]),
 }
@@ -164,6 +184,20 @@ class Library:
                 raise KeyError(key)
             setattr(cfg, key, val)
         return cfg
+
+    def ws_config(self, **kw):
+        cfg = WsConfig()
+        self.check(self.cdll.adasap_ws_config_default(ctypes.byref(cfg)))
+        for key, val in kw.items():
+            if key == "lambda":
+                key = "lam"
+            if not hasattr(cfg, key):
+                raise KeyError(key)
+            setattr(cfg, key, val)
+        return cfg
+
+    def warm_start(self, cfg, freqs, phases, params):
+        return WarmStart(self, cfg, freqs, phases, params)
 
     def workspace_bytes(self, cfg, n, d, k):
         return self.cdll.adasap_workspace_bytes(ctypes.byref(cfg), n, d, k)
@@ -244,6 +278,89 @@ class Library:
         reps = (Report * P)()
         self.check(self.cdll.adasap_solve_batch(probs, P, ctypes.byref(cfg), dtype, _stream(), reps))
         return [r.as_dict() for r in reps]
+
+
+class WarmStart:
+    """Learned warm start: a network trained on solved problems predicts the posterior mean
+    m^ of a new problem, giving W0 = (y - m^) / lambda.  All tensors float32 on the device."""
+
+    def __init__(self, lib, cfg, freqs, phases, params):
+        torch = _torch()
+        self.lib, self.cfg = lib, cfg
+        f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()
+        self._keep = [f32(freqs), f32(phases), f32(params)]
+        h = ctypes.c_void_p()
+        lib.check(lib.cdll.adasap_ws_create(ctypes.byref(cfg), _ptr(self._keep[0]), _ptr(self._keep[1]),
+                                            _ptr(self._keep[2]), _stream(), ctypes.byref(h)))
+        self.h = h
+        self.np = lib.cdll.adasap_ws_param_count(ctypes.byref(cfg))
+
+    def add_problem(self, X, y, W):
+        _check_dev(X, y, W)
+        self.lib.check(self.lib.cdll.adasap_ws_add_problem(self.h, X.shape[0], _ptr(X), _ptr(y), _ptr(W)))
+
+    def train_rows(self):
+        return self.lib.cdll.adasap_ws_train_rows(self.h)
+
+    def train(self, epochs, batch, lr, seed):
+        loss = np.zeros(max(1, epochs))
+        self.lib.check(self.lib.cdll.adasap_ws_train(self.h, epochs, batch, lr, seed,
+                                                     loss.ctypes.data_as(ctypes.c_void_p)))
+        return loss[:epochs]
+
+    def features(self, X, y):
+        torch = _torch()
+        _check_dev(X, y)
+        out = torch.empty((X.shape[0], self.cfg.D + 2), dtype=torch.float32, device=X.device)
+        theta = torch.empty(self.cfg.D, dtype=torch.float64, device=X.device)
+        self.lib.check(self.lib.cdll.adasap_ws_features(self.h, X.shape[0], _ptr(X), _ptr(y), _ptr(out),
+                                                        _ptr(theta)))
+        return out, theta
+
+    def loss_grad(self, A, t):
+        torch = _torch()
+        _check_dev(A, t)
+        g = torch.empty(self.np, dtype=torch.float32, device=A.device)
+        loss = ctypes.c_double()
+        self.lib.check(self.lib.cdll.adasap_ws_loss_grad(self.h, A.shape[0], _ptr(A), _ptr(t),
+                                                         ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def predict_mean(self, X, y):
+        torch = _torch()
+        _check_dev(X, y)
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        self.lib.check(self.lib.cdll.adasap_ws_predict_mean(self.h, X.shape[0], _ptr(X), _ptr(y), _ptr(out)))
+        return out
+
+    def initial_iterate(self, X, y):
+        torch = _torch()
+        _check_dev(X, y)
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        self.lib.check(self.lib.cdll.adasap_ws_initial_iterate(self.h, X.shape[0], _ptr(X), _ptr(y),
+                                                               _ptr(out)))
+        return out
+
+    def params(self):
+        torch = _torch()
+        out = torch.empty(self.np, dtype=torch.float32, device="cuda")
+        self.lib.check(self.lib.cdll.adasap_ws_get_params(self.h, _ptr(out)))
+        return out
+
+    def set_params(self, p):
+        _check_dev(p)
+        self.lib.check(self.lib.cdll.adasap_ws_set_params(self.h, _ptr(p)))
+
+    def close(self):
+        if self.h:
+            self.lib.cdll.adasap_ws_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Handle:

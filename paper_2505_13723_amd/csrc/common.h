@@ -81,6 +81,7 @@ __host__ __device__ inline u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
 constexpr uint64_t PURPOSE_B = 5;
 constexpr uint64_t PURPOSE_OMEGA = 6;
 constexpr uint64_t PURPOSE_POW = 7;
+constexpr uint64_t PURPOSE_MINIBATCH = 11;  // warm-start training order, epoch = t
 constexpr uint64_t PURPOSE_SWEEP_STRIDE = 16;
 
 // ---- device-resident scalars of one iteration (never copied back inside the loop) -----------

@@ -122,6 +122,8 @@ adasap_status_t normals_dev(uint64_t seed, uint64_t purpose, uint64_t t, int64_t
                             double* out, hipStream_t s, int P = 1);
 void sample_block_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n, int64_t b,
                        int64_t* out);
+// uniform permutation of [0, m) (Fisher-Yates on the stream (seed, purpose, t))
+void permutation_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t m, int64_t* out);
 
 // ---- gathers / Nesterov (update.hip) ------------------------------------------------------
 // dst[i, :] (type dt, cols c) = src[idx[i], :] (type st)

@@ -3,6 +3,7 @@
 //   uniform in (0,1]: ((w >> 11) + 1) 2^-53;  uniform in [0,1): (w >> 11) 2^-53
 //   normal number e: sqrt(-2 ln u1) cos(2 pi u2) with u1 from word 2e, u2 from word 2e+1
 //   bounded integer in [0, s): Lemire's multiply-shift with rejection
+//   permutation of [0, m): Fisher-Yates from the top, i swapped with bounded(i + 1)
 #include <algorithm>
 #include <unordered_set>
 #include <vector>
@@ -92,6 +93,17 @@ void sample_block_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n, i
     out[cnt++] = pick;
   }
   std::sort(out, out + b);
+}
+
+void permutation_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t m, int64_t* out) {
+  HostStream hs{seed, purpose, t};
+  for (int64_t i = 0; i < m; ++i) out[i] = i;
+  for (int64_t i = m - 1; i > 0; --i) {
+    const int64_t j = (int64_t)bounded(hs, (uint64_t)i + 1);
+    const int64_t tmp = out[i];
+    out[i] = out[j];
+    out[j] = tmp;
+  }
 }
 
 }  // namespace adasap

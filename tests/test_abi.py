@@ -22,7 +22,8 @@ def hlib():
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "adasap.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(adasap_[a-z_]+)\s*\(", text)))
 
@@ -99,3 +100,17 @@ def test_sample_block_rejects(hlib):
     p = out.ctypes.data_as(ctypes.c_void_p)
     assert hlib.cdll.adasap_sample_block(1, 5, 0, 3, 4, p) == 1
     assert hlib.cdll.adasap_sample_block(1, 5, 0, 3, 0, p) == 1
+
+
+def test_warm_start_param_count_and_config_validation(hlib):
+    from oracle import mlp as OM
+
+    cfg = hlib.ws_config(d=3, D=10, hidden=7)
+    assert hlib.cdll.adasap_ws_param_count(ctypes.byref(cfg)) == OM.param_count([12, 7, 7, 7, 1])
+    fake = ctypes.c_void_p(0x1000)
+    for field, value in [("D", 0), ("D", 2000), ("hidden", 0), ("d", 65), ("lam", 0.0), ("beta1", 1.0)]:
+        bad = hlib.ws_config(**{field: value})
+        assert hlib.cdll.adasap_ws_param_count(ctypes.byref(bad)) == 0
+        h = ctypes.c_void_p()
+        st = hlib.cdll.adasap_ws_create(ctypes.byref(bad), fake, fake, fake, None, ctypes.byref(h))
+        assert st == 1 and not h.value, (field, value)
