@@ -18,8 +18,14 @@ With --workload batched it instead times the 256-problem batch (n_p log-uniform 
 a step is one round, one ADASAP iteration of every problem with one persistent Step-I
 launch; `value` is the batch's aggregate kernel-block GFLOP/s.
 
+With --workload warm it times the learned warm start: 32 windows of one GP field (d = 9,
+RBF ell = 0.1, point density of 1e8 points in the unit cube) are solved by the batched
+solver, the network is trained on them, and a larger problem of the same field is solved
+to relative residual 1e-3 from zero and from the learned start (kept only if its residual
+after a one-pass probe beats the cold start's); `value` is the guarded time to residual.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-ttr] [--no-cpu]
-                       [--workload c3|batched]
+                       [--workload c3|batched|warm] [--ws-lam L] [--ws-n N]
 """
 import argparse
 import json
@@ -53,7 +59,9 @@ def main():
     ap.add_argument("--ttr-passes", type=int, default=40, help="data passes allowed for time-to-residual")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=384)
-    ap.add_argument("--workload", choices=["c3", "batched"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "batched", "warm"], default="c3")
+    ap.add_argument("--ws-lam", type=float, default=1.0, help="noise variance of the warm workload")
+    ap.add_argument("--ws-n", type=int, default=1 << 20, help="points of the warm-start target")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -65,6 +73,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args, torch, binding, inputs)
+    if args.workload == "warm":
+        return bench_warm(args, torch, binding, inputs)
     cfgw = dict(inputs.WORKLOADS["c3_rbf_n2m_k64"])
     n, d, k = args.n, cfgw["d"], cfgw["k"]
     b, r, lam, ell = cfgw["b"], cfgw["r"], cfgw["lam"], cfgw["ell"]
@@ -210,6 +220,107 @@ def bench_batched(args, torch, binding, inputs):
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_warm(args, torch, binding, inputs):
+    """Cold vs learned warm start on a problem drawn from the training windows' field."""
+    import numpy as np
+
+    w = inputs.WORKLOADS["ws_rbf_d9"]
+    d, ell, lam, D, H = w["d"], w["ell"], args.ws_lam, w["D"], w["H"]
+    n = args.ws_n
+    b = max(1024, n // 64)
+    lib = binding.load()
+    field = inputs.ws_field(w["seed"], d, ell, w["field_features"])
+    outer = inputs.box_side(n, w["density"], d)
+    side = inputs.box_side(w["n_window"], w["density"], d)
+    corners = inputs.ws_window_corners(w["seed"] + 1, w["windows"], d, outer, side)
+    Xs, ys, Ws = [], [], []
+    for p in range(w["windows"]):
+        X, y = inputs.ws_points(field, w["n_window"], corners[p], side, lam, 100 + p, device="cuda")
+        Xs.append(X.float().contiguous())
+        ys.append(y.float().contiguous())
+        Ws.append(torch.zeros(w["n_window"], dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cfgb = lib.config(kernel="rbf", lam=lam, block_size=1024, rank=128, max_iters=480, seed=7,
+                      precision="fp32", tol=1e-12)
+    reps = lib.solve_batch(cfgb, Xs, [y.view(-1, 1) for y in ys], [W.view(-1, 1) for W in Ws],
+                           [ell] * w["windows"])
+    t_label = time.perf_counter() - t0
+    cfg = lib.ws_config(d=d, D=D, hidden=H, lam=lam)
+    Wf, c = inputs.ws_rff(w["seed"] + 2, d, ell, D)
+    ws = lib.warm_start(cfg, Wf, c, inputs.ws_init_params(w["seed"] + 3, [D + 2, H, H, H, 1]))
+    t0 = time.perf_counter()
+    for p in range(w["windows"]):
+        ws.add_problem(Xs[p], ys[p], Ws[p])
+    losses = ws.train(epochs=12, batch=512, lr=1e-3, seed=11)
+    t_train = time.perf_counter() - t0
+    log("labels: worst relres %.2e in %.2f s; training %.2f s, losses %s"
+        % (max(r["relres"] for r in reps), t_label, t_train, np.round(losses, 4).tolist()))
+    X, y = inputs.ws_points(field, n, np.zeros(d), outer, lam, 999, device="cuda")
+    X, y = X.float().contiguous(), y.float().contiguous()
+    Y = y.view(-1, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W0 = ws.initial_iterate(X, y).view(-1, 1)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t0
+    per_pass = int(math.ceil(n / b))
+
+    def solve(start, iters, tol):
+        h = lib.create(lib.config(kernel="rbf", lengthscale=ell, lam=lam, block_size=b, rank=128,
+                                  max_iters=iters, seed=13, precision="fp32", tol=tol,
+                                  check_every=per_pass), X, Y)
+        rep = h.solve(start)
+        h.close()
+        return rep
+
+    h = lib.create(lib.config(kernel="rbf", lengthscale=ell, lam=lam, block_size=b, rank=128,
+                              precision="fp32"), X, Y)
+    relres_w0 = h.residual(W0)[0]
+    h.close()
+    # guard: one probe pass from each start, judged by the residual
+    probe = {}
+    for name, start in (("cold", torch.zeros_like(Y)), ("warm", W0.clone())):
+        probe[name] = solve(start, per_pass, 0.0)["relres"]
+    use_warm = probe["warm"] < probe["cold"]
+    out = {}
+    for name, start in (("cold", torch.zeros_like(Y)), ("warm", W0.clone())):
+        rep = solve(start, per_pass * args.ttr_passes, 1e-3)
+        ok = 0 <= rep["relres"] <= 1e-3
+        out[name] = {"seconds": rep["solve_ms"] / 1e3 if ok else None, "reached": bool(ok),
+                     "passes": rep["iters"] / per_pass, "relres": rep["relres"],
+                     "step1_kernel_ms": rep["step1_kernel_ms"] / max(1, rep["step1_launches"])}
+        log("%s: %s" % (name, json.dumps(out[name])))
+    chosen = out["warm"] if use_warm else out["cold"]
+    value = chosen["seconds"]
+    if value is not None and use_warm:
+        value += t_infer
+    kern_ms = out["cold"]["step1_kernel_ms"]
+    achieved = float(b) * n / (kern_ms * 1e-3) / 1e12
+    line = {
+        "metric": "time to rel. residual 1e-3 (s), learned warm start (guarded) vs cold, 1 GPU",
+        "value": None if value is None else round(value, 3), "unit": "s", "n_gpus": 1,
+        "steps": out["cold"]["passes"] * per_pass, "warmup": 0,
+        "ms_per_step": round(kern_ms, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (f16 hi/lo matrix-core distances), f64 Nystrom cores",
+        "data": "synthetic (one RBF prior field, 32 training windows, fresh target points)",
+        "config": {"workload": "warm_start_rbf_d9_n%d" % n, "n": n, "d": d, "lambda": lam,
+                   "lengthscale": ell, "b": b, "r": 128, "windows": w["windows"],
+                   "n_window": w["n_window"], "D": D, "hidden": H, "epochs": 12},
+        "warm_start": {"probe_relres": probe, "used": bool(use_warm), "cold": out["cold"],
+                       "warm": out["warm"], "inference_seconds": round(t_infer, 4),
+                       "training_seconds": round(t_train, 3), "label_seconds": round(t_label, 3),
+                       "relres_at_W0": relres_w0},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
+                     "unit": "Texp/s", "frac": round(achieved / PEAK_EXP_TPS, 4), "traffic": None,
+                     "kernel": "mk_kernel (Step-I product, float32 vector mode)",
+                     "kernel_ms": round(kern_ms, 4)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    ws.close()
 
 
 def cpu_baseline_batched(host, ds, ells, b):

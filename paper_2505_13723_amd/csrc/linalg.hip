@@ -74,22 +74,46 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int splits, 
   P[e] = s;
 }
 
+// The same sum over many partials: one block per output entry, a strided sum per thread
+// and a fixed-order tree.
+__global__ __launch_bounds__(256) void gram_reduce_tree_kernel(const double* __restrict__ part,
+                                                               int splits, int p, int q,
+                                                               const double* __restrict__ rowscale,
+                                                               double* __restrict__ P, Batch bat) {
+  __shared__ double red[256];
+  const int e = blockIdx.x;
+  const int prob = blockIdx.y;
+  part += (int64_t)prob * splits * p * q;
+  P += prob * bat.sC;
+  if (rowscale) rowscale += prob * bat.sD;
+  double s = 0.0;
+  for (int sp = threadIdx.x; sp < splits; sp += 256) s += part[(int64_t)sp * p * q + e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) P[e] = rowscale ? red[0] * rowscale[e / q] : red[0];
+}
+
 // Gram products with a thin right factor (q <= 4): one thread per column of A, rows in
-// two interleaved halves, so every load of a row of A is coalesced.
-constexpr int GV_CHUNK = 512;
+// two interleaved halves, so every load of a row of A is coalesced.  Row chunks are sized
+// so that a launch has about 256 workgroups (at least 64 rows each).
 __global__ __launch_bounds__(256) void gramv_partial_kernel(int64_t rows, int p, int q,
                                                             const void* __restrict__ A, DT at,
                                                             int64_t lda, const void* __restrict__ B,
                                                             DT bt, int64_t ldb,
-                                                            double* __restrict__ part, Batch bat) {
+                                                            double* __restrict__ part, Batch bat,
+                                                            int64_t chunk) {
   __shared__ double red[128 * 4];
   const int prob = blockIdx.y;
   A = adv(A, at, prob * bat.sA);
   B = adv(B, bt, prob * bat.sB);
   part += (int64_t)prob * gridDim.x * p * q;
   const int col = threadIdx.x % 128, half = threadIdx.x / 128;
-  const int64_t r0 = (int64_t)blockIdx.x * GV_CHUNK;
-  const int64_t r1 = r0 + GV_CHUNK < rows ? r0 + GV_CHUNK : rows;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (col < p) {
     for (int64_t row = r0 + half; row < r1; row += 2) {
@@ -323,14 +347,24 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
 // ---------------------------------------------------------------- Jacobi eigensolver
 // Parallel cyclic Jacobi: each step applies r/2 disjoint rotations (round-robin pairing),
 // H <- J^T H J, as independent 2x2-block updates (block (a, b) mixes rows of pair a with
-// columns of pair b), one LDS pass per step.  The row stride is padded to RMAX + 1 doubles
-// so that the column reads of a wave fall in different LDS banks.
+// columns of pair b), one LDS pass per step over the upper triangle only.
 constexpr int JAC_MAX_SWEEPS = 16;
-constexpr int HS = RMAX + 1;  // padded row stride
 
 __device__ inline int rr_index(int i, int step, int rp) {
   // circle method: player 0 fixed, the others rotate by `step`
   return i == 0 ? 0 : 1 + (i - 1 + step) % (rp - 1);
+}
+
+// Symmetric storage: the upper triangle of the (padded) rp x rp matrix, row-major, so that
+// element (i, j), i <= j, sits at i rp - i (i + 1) / 2 + j.  A step updates each unordered pair
+// of rotation pairs {a, b} once (a <= b); its four entries are distinct stored elements.
+__device__ inline int sym_idx(int i, int j, int rp) {
+  if (i > j) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
+  return i * rp - (i * (i + 1)) / 2 + j;
 }
 
 __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __restrict__ Hg,
@@ -338,7 +372,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
                                                       double* __restrict__ rot,
                                                       IterScalars* __restrict__ sc,
                                                       int64_t rot_cap) {
-  __shared__ double H[RMAX * HS];
+  __shared__ double H[RMAX * (RMAX + 1) / 2];
+  __shared__ unsigned short tab[(RMAX / 2) * (RMAX / 2 + 1) / 2];
   Hg += (int64_t)blockIdx.x * r * r;
   evals += (int64_t)blockIdx.x * r;
   rot += (int64_t)blockIdx.x * rot_cap;
@@ -350,15 +385,23 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
   const int tid = threadIdx.x;
   const int rp = r + (r & 1);
   const int half = rp / 2;
+  const int nblk = half * (half + 1) / 2;
   // the padded dummy index (odd r) has a zero row and column and is never rotated
-  for (int e = tid; e < rp * rp; e += 1024) {
-    const int i = e / rp, j = e % rp;
-    H[i * HS + j] = (i < r && j < r) ? Hg[i * r + j] : 0.0;
+  for (int i = tid; i < rp; i += 1024)
+    for (int j = i; j < rp; ++j) H[sym_idx(i, j, rp)] = (i < r && j < r) ? Hg[i * r + j] : 0.0;
+  // table of the pair-of-pairs blocks (a, b), a <= b
+  for (int e = tid; e < nblk; e += 1024) {
+    int a = 0, rem = e;
+    while (rem >= half - a) {
+      rem -= half - a;
+      ++a;
+    }
+    tab[e] = (unsigned short)((a << 8) | (a + rem));
   }
   __syncthreads();
   if (tid == 0) {
     double m = 0.0;
-    for (int i = 0; i < r; ++i) m = fmax(m, fabs(H[i * HS + i]));
+    for (int i = 0; i < r; ++i) m = fmax(m, fabs(H[sym_idx(i, i, rp)]));
     hmax = m;
   }
   __syncthreads();
@@ -373,8 +416,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
         const int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, s = 0.0;
         if (q < r) {
-          const double apq = H[p * HS + q];
-          const double app = H[p * HS + p], aqq = H[q * HS + q];
+          const double apq = H[sym_idx(p, q, rp)];
+          const double app = H[sym_idx(p, p, rp)], aqq = H[sym_idx(q, q, rp)];
           if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_floor)) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = fabs(tau) > 1e150 ? 0.5 / tau
@@ -393,28 +436,32 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
         rot[2 * slot + 1] = s;
       }
       __syncthreads();
-      for (int e = tid; e < half * half; e += 1024) {
-        const int a = e / half, bb = e % half;
+      for (int e = tid; e < nblk; e += 1024) {
+        const int a = tab[e] >> 8, bb = tab[e] & 255;
         const double sa = cs_s[a], sb = cs_s[bb];
         if (sa == 0.0 && sb == 0.0) continue;
         const double ca = cs_c[a], cb = cs_c[bb];
         const int pa = pp[a], qa = qq[a], pb = pp[bb], qb = qq[bb];
-        const double h11 = H[pa * HS + pb], h12 = H[pa * HS + qb];
-        const double h21 = H[qa * HS + pb], h22 = H[qa * HS + qb];
+        const int i11 = sym_idx(pa, pb, rp), i12 = sym_idx(pa, qb, rp);
+        const int i21 = sym_idx(qa, pb, rp), i22 = sym_idx(qa, qb, rp);
+        const double h11 = H[i11], h12 = H[i12], h21 = H[i21], h22 = H[i22];
         // rows: J_a^T
         const double r11 = ca * h11 - sa * h21, r12 = ca * h12 - sa * h22;
         const double r21 = sa * h11 + ca * h21, r22 = sa * h12 + ca * h22;
         // columns: J_b
-        double n11 = cb * r11 - sb * r12, n12 = sb * r11 + cb * r12;
-        double n21 = cb * r21 - sb * r22, n22 = sb * r21 + cb * r22;
-        if (a == bb && sa != 0.0) {
-          n12 = 0.0;  // the rotation annihilates the pair's off-diagonal entry
-          n21 = 0.0;
+        const double n11 = cb * r11 - sb * r12, n12 = sb * r11 + cb * r12;
+        const double n21 = cb * r21 - sb * r22, n22 = sb * r21 + cb * r22;
+        if (a == bb) {
+          // diagonal block (pa < qa): i12 == i21; the rotation annihilates the off-diagonal entry
+          H[i11] = n11;
+          H[i12] = sa != 0.0 ? 0.0 : n12;
+          H[i22] = n22;
+        } else {
+          H[i11] = n11;
+          H[i12] = n12;
+          H[i21] = n21;
+          H[i22] = n22;
         }
-        H[pa * HS + pb] = n11;
-        H[pa * HS + qb] = n12;
-        H[qa * HS + pb] = n21;
-        H[qa * HS + qb] = n22;
       }
       __syncthreads();
     }
@@ -423,7 +470,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
     if (done == 0) break;
     sweeps_used = sweep + 1;
   }
-  for (int i = tid; i < r; i += 1024) evals[i] = H[i * HS + i];
+  for (int i = tid; i < r; i += 1024) evals[i] = H[sym_idx(i, i, rp)];
   if (tid == 0) sc->sweeps = sweeps_used;
 }
 
@@ -612,18 +659,24 @@ adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t l
                      hipStream_t s, const Batch& bat) {
   const int NP = bat.P;
   if (q <= 4 && p <= 128) {
-    int sp = (int)((rows + GV_CHUNK - 1) / GV_CHUNK);
+    int64_t chunk = (rows + 255) / 256;
+    chunk = chunk < 64 ? 64 : (chunk + 1) / 2 * 2;
+    int sp = (int)((rows + chunk - 1) / chunk);
     if (sp < 1) sp = 1;
     ADASAP_TRY(part.ensure((size_t)NP * sp * p * q * sizeof(double)));
     if (rows > 0) {
       hipLaunchKernelGGL(gramv_partial_kernel, dim3(sp, NP), dim3(256), 0, s, rows, p, q, A, at, lda,
-                         B, bt, ldb, part.as<double>(), bat);
+                         B, bt, ldb, part.as<double>(), bat, chunk);
       ADASAP_LAUNCH_CHECK();
     } else {
       ADASAP_HIP(hipMemsetAsync(part.p, 0, (size_t)NP * p * q * sizeof(double), s));
     }
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256, NP), dim3(256), 0, s,
-                       part.as<double>(), sp, p, q, rowscale, P, bat);
+    if (sp >= 32)
+      hipLaunchKernelGGL(gram_reduce_tree_kernel, dim3(p * q, NP), dim3(256), 0, s,
+                         part.as<double>(), sp, p, q, rowscale, P, bat);
+    else
+      hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256, NP), dim3(256), 0, s,
+                         part.as<double>(), sp, p, q, rowscale, P, bat);
     ADASAP_LAUNCH_CHECK();
     return ADASAP_OK;
   }

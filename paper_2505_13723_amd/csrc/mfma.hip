@@ -147,27 +147,34 @@ __global__ void colpack_kernel(const _Float16* __restrict__ rowv, const int64_t*
 // (non-negative floats order like their bit patterns)
 __global__ __launch_bounds__(256) void colmax_partial_kernel(const void* __restrict__ R, DT rt,
                                                              int64_t rows, int k, int64_t ldr,
-                                                             float* __restrict__ part) {
+                                                             float* __restrict__ part, int64_t rpb) {
   __shared__ unsigned int mx[128];
   R = static_cast<const char*>(R) + (int64_t)blockIdx.y * rows * ldr * (rt == DT::F64 ? 8 : 4);
   part += (int64_t)blockIdx.y * gridDim.x * k;
   for (int c = threadIdx.x; c < k; c += 256) mx[c] = 0u;
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * 4096;
-  const int64_t r1 = r0 + 4096 < rows ? r0 + 4096 : rows;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = r0 + rpb < rows ? r0 + rpb : rows;
   const int64_t cnt = (r1 - r0) * k;
   if (256 % k == 0) {
-    // every element a thread visits lies in column threadIdx.x % k: keep the maximum in a register
+    // thread t reads column t % k of rows t / k, t / k + 256 / k, ...: a register maximum
+    const int c = threadIdx.x % k;
+    const int rstep = 256 / k;
     float m = 0.0f;
-    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
-      const int64_t row = r0 + e / k;
-      const int c = (int)(e % k);
-      const double v = rt == DT::F64 ? static_cast<const double*>(R)[row * ldr + c]
-                                     : (double)static_cast<const float*>(R)[row * ldr + c];
-      const float a = (float)fabs(v);
-      m = fmaxf(m, isfinite(a) ? a : 3.0e38f);
+    if (rt == DT::F64) {
+      const double* Rd = static_cast<const double*>(R);
+      for (int64_t row = r0 + threadIdx.x / k; row < r1; row += rstep) {
+        const float a = (float)fabs(Rd[row * ldr + c]);
+        m = fmaxf(m, isfinite(a) ? a : 3.0e38f);
+      }
+    } else {
+      const float* Rf = static_cast<const float*>(R);
+      for (int64_t row = r0 + threadIdx.x / k; row < r1; row += rstep) {
+        const float a = fabsf(Rf[row * ldr + c]);
+        m = fmaxf(m, isfinite(a) ? a : 3.0e38f);
+      }
     }
-    atomicMax(&mx[threadIdx.x % k], __float_as_uint(m));
+    atomicMax(&mx[c], __float_as_uint(m));
   } else {
     for (int64_t e = threadIdx.x; e < cnt; e += 256) {
       const int64_t row = r0 + e / k;
@@ -182,24 +189,41 @@ __global__ __launch_bounds__(256) void colmax_partial_kernel(const void* __restr
   for (int c = threadIdx.x; c < k; c += 256) part[(int64_t)blockIdx.x * k + c] = __uint_as_float(mx[c]);
 }
 
-// scale[c] = power of two with max|R[:, c]| / scale <= 2^14 (scale >= 2^-60), 1 if the column is 0
-__global__ void colmax_final_kernel(const float* __restrict__ part, int nblk, int k,
-                                    float* __restrict__ scale) {
-  part += (int64_t)blockIdx.x * nblk * k;
-  scale += (int64_t)blockIdx.x * k;
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    float m = 0.0f;
-    for (int b = 0; b < nblk; ++b) m = fmaxf(m, part[(int64_t)b * k + c]);
-    float s = 1.0f;
+// scale[c] = power of two with max|R[:, c]| / scale <= 2^14 (scale >= 2^-60), 1 if the column is 0.
+// One block per (column, problem): a strided maximum over the partials, then a tree.
+__global__ __launch_bounds__(256) void colmax_final_kernel(const float* __restrict__ part, int nblk,
+                                                           int k, float* __restrict__ scale) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  part += (int64_t)blockIdx.y * nblk * k;
+  scale += (int64_t)blockIdx.y * k;
+  float m = 0.0f;
+  for (int b = threadIdx.x; b < nblk; b += 256) m = fmaxf(m, part[(int64_t)b * k + c]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    m = red[0];
+    float sc = 1.0f;
     if (m > 0.0f && isfinite(m)) {
       int ex;
-      frexpf(m, &ex);             // m = f 2^ex, f in [0.5, 1)
+      frexpf(m, &ex);  // m = f 2^ex, f in [0.5, 1)
       int p = ex - 14;
       if (p < -60) p = -60;
-      s = ldexpf(1.0f, p);
+      sc = ldexpf(1.0f, p);
     }
-    scale[c] = s;
+    scale[c] = sc;
   }
+}
+
+// rows per block of the column-maximum partials: at least 64, about 2048 blocks
+inline int64_t colmax_rows_per_block(int64_t rows) {
+  int64_t rpb = (rows + 2047) / 2048;
+  rpb = (rpb + 63) / 64 * 64;
+  return rpb < 64 ? 64 : rpb;
 }
 
 // float16 right-hand-side fragments: tile T, tile q of 16 columns, part (hi, lo), lane, slot m
@@ -310,8 +334,10 @@ struct MkArgs {
   const int64_t* rhs_off;   // per problem, bytes
 };
 
+// two workgroups (eight waves) per CU; the hi/lo products with more than 64 right-hand
+// sides keep one, so their accumulators fit in registers without spilling
 template <int MODE, int NQ>
-constexpr int mk_occupancy() { return 2; }
+constexpr int mk_occupancy() { return (MODE == MODE_F16X3 && NQ > 4) ? 1 : 2; }
 
 template <int KS, int MODE, int NQ>
 struct MkShape {
@@ -365,25 +391,30 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
   // barrier per tile: while the waves compute tile T from one LDS buffer, tile T+1 is written
   // to the other and tile T+2 is in flight in registers
   constexpr int LOADS16 = (A_FR + R_FR + (R_F32 * 4) / 16 + 255) / 256;
-  uint4 stA[LOADS16], stB[LOADS16];
+  struct Stage {
+    uint4 v[LOADS16];
+  };
   // branch-free loads (one basic block, so the wait before each LDS store covers exactly the
-  // older of the two register stages); lanes past the tile's data read a valid dummy address
-  auto gload = [&](uint4 (&st)[LOADS16], int64_t T) {
+  // older of the two register stages); lanes past the tile's data read a valid dummy address.
+  // Stages are passed by value so that they stay in registers.
+  auto gload = [&](int64_t T) __attribute__((always_inline)) -> Stage {
+    Stage st;
     const uint4* ca = reinterpret_cast<const uint4*>(colA_p) + T * A_FR;
     const uint4* rb = reinterpret_cast<const uint4*>(rhs_p) + T * (R_FR + (R_F32 * 4) / 16);
 #pragma unroll
     for (int u = 0; u < LOADS16; ++u) {
       const int e = tid + u * 256;
       const uint4* src = e < A_FR ? ca + e : (e < TOTAL16 ? rb + (e - A_FR) : ca);
-      st[u] = *src;
+      st.v[u] = *src;
     }
+    return st;
   };
-  auto sstore = [&](const uint4 (&st)[LOADS16], int buf) {
+  auto sstore = [&](const Stage& st, int buf) __attribute__((always_inline)) {
     uint4* dst = reinterpret_cast<uint4*>(lds + buf * BUF_BYTES);
 #pragma unroll
-    for (int u = 0; u < LOADS16; ++u) dst[tid + u * 256] = st[u];
+    for (int u = 0; u < LOADS16; ++u) dst[tid + u * 256] = st.v[u];
   };
-  auto compute = [&](int buf) {
+  auto compute = [&](int buf) __attribute__((always_inline)) {
     const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
     half8 A[2][KS];
 #pragma unroll
@@ -442,22 +473,23 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
   if (T0 < T1) {
     // tiles past the end are clamped to the last one: loaded and stored but never computed
     auto tc = [&](int64_t T) { return T < T1 ? T : T1 - 1; };
-    gload(stA, T0);
-    sstore(stA, 0);
-    gload(stB, tc(T0 + 1));
+    Stage s0 = gload(T0);
+    sstore(s0, 0);
+    Stage s1 = gload(tc(T0 + 1));
     __syncthreads();
-    for (int64_t T = T0; T < T1; T += 2) {
-      // buffer 0 holds tile T; stB holds (or is receiving) tile T+1
-      gload(stA, tc(T + 2));
+    int64_t T = T0;
+    // pairs of tiles: on entry LDS buffer 0 holds tile T and s1 holds tile T + 1
+    for (; T + 1 < T1; T += 2) {
+      s0 = gload(tc(T + 2));
       compute(0);
-      sstore(stB, 1);
+      sstore(s1, 1);
       __syncthreads();
-      if (T + 1 >= T1) break;
-      gload(stB, tc(T + 3));
+      s1 = gload(tc(T + 3));
       compute(1);
-      sstore(stA, 0);
+      sstore(s0, 0);
       __syncthreads();
     }
+    if (T < T1) compute(0);  // odd count: the last tile is in buffer 0
   }
 
   // write partial sums
@@ -728,7 +760,8 @@ adasap_status_t pack_rhs(const void* R, DT rt, int64_t rows, int k, int64_t ldr,
   ADASAP_TRY(buf.ensure((size_t)ntiles * nq * parts * 64 * 16));
   ADASAP_TRY(scale.ensure((size_t)k * sizeof(float)));
   // column maxima of the (gathered) right-hand side
-  const int nblk = (int)((rows + 4095) / 4096);
+  const int64_t rpb = colmax_rows_per_block(rows);
+  const int nblk = (int)((rows + rpb - 1) / rpb);
   ADASAP_TRY(tmp.ensure((size_t)(nblk > 0 ? nblk : 1) * k * sizeof(float)));
   if (idx) {
     // gathered rows: maxima over all of R are a valid (larger or equal) bound
@@ -737,10 +770,10 @@ adasap_status_t pack_rhs(const void* R, DT rt, int64_t rows, int k, int64_t ldr,
   }
   if (nblk > 0) {
     hipLaunchKernelGGL(colmax_partial_kernel, dim3(nblk), dim3(256), 0, s, R, rt, rows, k, ldr,
-                       tmp.as<float>());
+                       tmp.as<float>(), rpb);
     ADASAP_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(colmax_final_kernel, dim3(1), dim3(128), 0, s, tmp.as<float>(), nblk, k,
+  hipLaunchKernelGGL(colmax_final_kernel, dim3(k), dim3(256), 0, s, tmp.as<float>(), nblk, k,
                      scale.as<float>());
   ADASAP_LAUNCH_CHECK();
   const int64_t tot = ntiles * nq * 64;
@@ -1017,11 +1050,12 @@ adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t*
     const int parts = mode == MODE_F16X3 ? 2 : 1;
     ADASAP_TRY(w.rhs.ensure((size_t)P * nt * nq * parts * 64 * 16));
     ADASAP_TRY(w.scale.ensure((size_t)P * k * sizeof(float)));
-    const int nblk = (int)((b + 4095) / 4096);
+    const int64_t rpb = colmax_rows_per_block(b);
+    const int nblk = (int)((b + rpb - 1) / rpb);
     ADASAP_TRY(w.tmp.ensure((size_t)P * nblk * k * sizeof(float)));
     hipLaunchKernelGGL(colmax_partial_kernel, dim3(nblk, P), dim3(256), 0, s, R, DT::F64, b, k, k,
-                       w.tmp.as<float>());
-    hipLaunchKernelGGL(colmax_final_kernel, dim3(P), dim3(128), 0, s, w.tmp.as<float>(), nblk, k,
+                       w.tmp.as<float>(), rpb);
+    hipLaunchKernelGGL(colmax_final_kernel, dim3(k, P), dim3(256), 0, s, w.tmp.as<float>(), nblk, k,
                        w.scale.as<float>());
     const int64_t tot = nt * nq * 64;
     hipLaunchKernelGGL(rhspack16_kernel, dim3((unsigned)((tot + 255) / 256), P), dim3(256), 0, s, R,
