@@ -155,6 +155,9 @@ class Library:
             raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() or "
                                "python -m paper_2505_13723_amd.build" % path)
         self.path = path
+        # torch first: the library then binds to the HIP runtime torch already loaded, so that
+        # both share one runtime (one device context, one allocator view)
+        _torch()
         self.cdll = ctypes.CDLL(path)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(self.cdll, name)

@@ -26,12 +26,18 @@ constexpr int G_T = 16;      // output tile
 constexpr int G_ROWS = 32;   // rows staged per step
 constexpr int G_CHUNK = 1024;  // rows per split
 
+// The small dense kernels of the Nystrom factors and of powering run on a second stream
+// beside the long kernel-block product; a raised wave priority lets their (few) waves win
+// instruction issue on the SIMDs they share with it.
+__device__ inline void raise_wave_priority() { __builtin_amdgcn_s_setprio(2); }
+
 __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int p, int q,
                                                            const void* __restrict__ A, DT at,
                                                            int64_t lda, const void* __restrict__ B,
                                                            DT bt, int64_t ldb,
                                                            double* __restrict__ part, int nsplit,
                                                            Batch bat) {
+  raise_wave_priority();
   __shared__ double As[G_ROWS][G_T];
   __shared__ double Bs[G_ROWS][G_T];
   const int prob = blockIdx.z / nsplit, split = blockIdx.z % nsplit;
@@ -62,6 +68,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int p, 
 __global__ void gram_reduce_kernel(const double* __restrict__ part, int splits, int p, int q,
                                    const double* __restrict__ rowscale, double* __restrict__ P,
                                    Batch bat) {
+  raise_wave_priority();
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= p * q) return;
   const int prob = blockIdx.y;
@@ -80,6 +87,7 @@ __global__ __launch_bounds__(256) void gram_reduce_tree_kernel(const double* __r
                                                                int splits, int p, int q,
                                                                const double* __restrict__ rowscale,
                                                                double* __restrict__ P, Batch bat) {
+  raise_wave_priority();
   __shared__ double red[256];
   const int e = blockIdx.x;
   const int prob = blockIdx.y;
@@ -106,6 +114,7 @@ __global__ __launch_bounds__(256) void gramv_partial_kernel(int64_t rows, int p,
                                                             DT bt, int64_t ldb,
                                                             double* __restrict__ part, Batch bat,
                                                             int64_t chunk) {
+  raise_wave_priority();
   __shared__ double red[128 * 4];
   const int prob = blockIdx.y;
   A = adv(A, at, prob * bat.sA);
@@ -138,6 +147,7 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int
                                                         const double* __restrict__ E, int64_t lde,
                                                         const double* __restrict__ alpha_ptr,
                                                         int alpha_mode, Batch bat) {
+  raise_wave_priority();
   __shared__ double Ms[128 * 4];
   const int prob = blockIdx.y;
   A += prob * bat.sA;
@@ -183,6 +193,7 @@ __global__ __launch_bounds__(256) void gemm_rm_kernel(int64_t rows, int p, int q
                                                       const double* __restrict__ E, int64_t lde,
                                                       const double* __restrict__ alpha_ptr,
                                                       int alpha_mode, Batch bat) {
+  raise_wave_priority();
   __shared__ double As[M_T][M_T + 1];
   const int prob = blockIdx.z;
   A += prob * bat.sA;
@@ -236,12 +247,19 @@ __global__ __launch_bounds__(256) void gemm_rm_kernel(int64_t rows, int p, int q
 }
 
 // ---------------------------------------------------------------- Nystrom core
+// The r x r core lives in LDS as its upper triangle, packed row by row (element (i, j), i <= j,
+// at i r - i (i + 1) / 2 + j): the Cholesky factor R overwrites it, then R^{-1} overwrites R in
+// place, so the kernel needs about half the LDS of a full square (and finds room on a CU that
+// a concurrent product kernel shares).
+__device__ inline int up_idx(int i, int j, int r) { return i * r - (i * (i + 1)) / 2 + j; }
+
 __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __restrict__ Mo,
                                                         const double* __restrict__ Qo, double eps,
                                                         double* __restrict__ Rinv,
                                                         double* __restrict__ Rg,
                                                         IterScalars* __restrict__ sc) {
-  __shared__ double C[RMAX * (RMAX + 1)];
+  raise_wave_priority();
+  __shared__ double C[RMAX * (RMAX + 1) / 2];
   {
     const int64_t off = (int64_t)blockIdx.x * r * r;
     Mo += off;
@@ -250,7 +268,7 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
     if (Rg) Rg += off;
     sc += blockIdx.x;
   }
-  __shared__ double xd[RMAX];
+  __shared__ double xt[RMAX];
   __shared__ int flag;
   __shared__ double s_delta;
   const int tid = threadIdx.x;
@@ -267,25 +285,25 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
     const double delta = s_delta;
     for (int e = tid; e < r * r; e += 1024) {
       const int i = e / r, j = e % r;
-      C[i * (RMAX + 1) + j] = 0.5 * (Mo[i * r + j] + Mo[j * r + i]) + delta * Qo[i * r + j];
+      if (j >= i) C[up_idx(i, j, r)] = 0.5 * (Mo[i * r + j] + Mo[j * r + i]) + delta * Qo[i * r + j];
     }
     __syncthreads();
-    // right-looking Cholesky: C = R^T R, R upper, stored in the upper triangle of C
+    // right-looking Cholesky: C = R^T R, R upper
     for (int kk = 0; kk < r; ++kk) {
       if (tid == 0) {
-        const double piv = C[kk * (RMAX + 1) + kk];
+        const double piv = C[up_idx(kk, kk, r)];
         if (!(piv > 0.0)) flag = 1;
-        else C[kk * (RMAX + 1) + kk] = sqrt(piv);
+        else C[up_idx(kk, kk, r)] = sqrt(piv);
       }
       __syncthreads();
       if (flag) break;
-      const double dk = C[kk * (RMAX + 1) + kk];
-      for (int j = kk + 1 + tid; j < r; j += 1024) C[kk * (RMAX + 1) + j] /= dk;
+      const double dk = C[up_idx(kk, kk, r)];
+      for (int j = kk + 1 + tid; j < r; j += 1024) C[up_idx(kk, j, r)] /= dk;
       __syncthreads();
       const int w = r - kk - 1;
       for (int e = tid; e < w * w; e += 1024) {
         const int i = kk + 1 + e / w, j = kk + 1 + e % w;
-        if (j >= i) C[i * (RMAX + 1) + j] -= C[kk * (RMAX + 1) + i] * C[kk * (RMAX + 1) + j];
+        if (j >= i) C[up_idx(i, j, r)] -= C[up_idx(kk, i, r)] * C[up_idx(kk, j, r)];
       }
       __syncthreads();
     }
@@ -315,32 +333,31 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
   if (Rg)
     for (int e = tid; e < r * r; e += 1024) {
       const int i = e / r, j = e % r;
-      Rg[e] = j >= i ? C[i * (RMAX + 1) + j] : 0.0;
+      Rg[e] = j >= i ? C[up_idx(i, j, r)] : 0.0;
     }
-  // X = R^{-1} (upper).  X[i][j] for i < j is kept in C[j][i] (strictly lower part),
-  // X[j][j] in xd[j]; rows i are processed from the bottom, 8 threads per column j.
+  // X = R^{-1} (upper) in place, rows i from the bottom: X[i][j] = -(sum_{l=i+1..j} R[i][l]
+  // X[l][j]) / R[i][i] uses row i of R (still in place) and the rows below it (already X);
+  // the new row goes through xt and is written back after a barrier.  8 threads per column.
   const int j = tid / 8, part = tid % 8;
   for (int i = r - 1; i >= 0; --i) {
-    if (j < r && j >= i) {
-      if (j == i) {
-        if (part == 0) xd[j] = 1.0 / C[i * (RMAX + 1) + i];
-      } else {
-        double s = 0.0;
-        for (int l = i + 1 + part; l <= j; l += 8) {
-          const double xl = (l == j) ? xd[j] : C[j * (RMAX + 1) + l];
-          s += C[i * (RMAX + 1) + l] * xl;
-        }
-        s += __shfl_xor(s, 1, 8);
-        s += __shfl_xor(s, 2, 8);
-        s += __shfl_xor(s, 4, 8);
-        if (part == 0) C[j * (RMAX + 1) + i] = -s / C[i * (RMAX + 1) + i];
-      }
+    if (j < r && j > i) {
+      double s = 0.0;
+      for (int l = i + 1 + part; l <= j; l += 8) s += C[up_idx(i, l, r)] * C[up_idx(l, j, r)];
+      s += __shfl_xor(s, 1, 8);
+      s += __shfl_xor(s, 2, 8);
+      s += __shfl_xor(s, 4, 8);
+      if (part == 0) xt[j] = -s / C[up_idx(i, i, r)];
+    }
+    __syncthreads();
+    if (j < r && j >= i && part == 0) {
+      if (j == i) C[up_idx(i, i, r)] = 1.0 / C[up_idx(i, i, r)];
+      else C[up_idx(i, j, r)] = xt[j];
     }
     __syncthreads();
   }
   for (int e = tid; e < r * r; e += 1024) {
     const int a = e / r, b = e % r;
-    Rinv[e] = a == b ? xd[a] : (a < b ? C[b * (RMAX + 1) + a] : 0.0);
+    Rinv[e] = a <= b ? C[up_idx(a, b, r)] : 0.0;
   }
 }
 
@@ -372,6 +389,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
                                                       double* __restrict__ rot,
                                                       IterScalars* __restrict__ sc,
                                                       int64_t rot_cap) {
+  raise_wave_priority();
   __shared__ double H[RMAX * (RMAX + 1) / 2];
   __shared__ unsigned short tab[(RMAX / 2) * (RMAX / 2 + 1) / 2];
   Hg += (int64_t)blockIdx.x * r * r;
@@ -480,11 +498,13 @@ constexpr int ACC_ROWS = 4;
 __global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
                                                            const IterScalars* __restrict__ sc,
                                                            double* __restrict__ V, int64_t rot_cap) {
+  raise_wave_priority();
   rot += (int64_t)blockIdx.y * rot_cap;
   sc += blockIdx.y;
   V += (int64_t)blockIdx.y * r * r;
+  constexpr int ACC_STEPS = 32;  // rotation steps staged in LDS at a time
   __shared__ double Vs[ACC_ROWS][RMAX];
-  __shared__ double R[(RMAX - 1) * (RMAX / 2) * 2];
+  __shared__ double R[ACC_STEPS * (RMAX / 2) * 2];
   const int tid = threadIdx.x;
   const int rp = r + (r & 1);
   const int half = rp / 2;
@@ -497,14 +517,20 @@ __global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* 
   const int per_sweep = (rp - 1) * half;
   const int ir = tid / 64, k = tid % 64;
   for (int sw = 0; sw < sweeps; ++sw) {
-    __syncthreads();
-    for (int e = tid; e < 2 * per_sweep; e += 256) R[e] = rot[(int64_t)sw * 2 * per_sweep + e];
-    __syncthreads();
     for (int step = 0; step < rp - 1; ++step) {
+      const int ls = step % ACC_STEPS;
+      if (ls == 0) {
+        // stage the rotations of steps [step, step + ACC_STEPS) of this sweep
+        __syncthreads();
+        const int nst = (rp - 1 - step) < ACC_STEPS ? (rp - 1 - step) : ACC_STEPS;
+        const int64_t base = ((int64_t)sw * per_sweep + (int64_t)step * half) * 2;
+        for (int e = tid; e < 2 * nst * half; e += 256) R[e] = rot[base + e];
+        __syncthreads();
+      }
       if (k < half && row0 + ir < r) {
-        const double s = R[2 * (step * half + k) + 1];
+        const double s = R[2 * (ls * half + k) + 1];
         if (s != 0.0) {
-          const double c = R[2 * (step * half + k)];
+          const double c = R[2 * (ls * half + k)];
           const int a = rr_index(k, step, rp), b = rr_index(rp - 1 - k, step, rp);
           const int p = a < b ? a : b, q = a < b ? b : a;
           const double vp = Vs[ir][p], vq = Vs[ir][q];
@@ -527,6 +553,7 @@ __global__ void nys_finalize_kernel(int r, const double* __restrict__ evals,
                                     double rho_fixed, double* __restrict__ S,
                                     double* __restrict__ T, double* __restrict__ cinv,
                                     double* __restrict__ cisq, IterScalars* __restrict__ sc) {
+  raise_wave_priority();
   __shared__ int perm[RMAX];
   {
     const int pb = blockIdx.x;
@@ -582,6 +609,7 @@ constexpr int DOT_PER_BLOCK = 4096;
 
 __global__ void dots_partial_kernel(int64_t n, const double* __restrict__ v,
                                     const double* __restrict__ z, double* __restrict__ part) {
+  raise_wave_priority();
   __shared__ double s1[DOT_BLOCK], s2[DOT_BLOCK];
   v += (int64_t)blockIdx.y * n;
   z += (int64_t)blockIdx.y * n;
@@ -611,6 +639,7 @@ __global__ void dots_partial_kernel(int64_t n, const double* __restrict__ v,
 
 __global__ void dots_final_kernel(const double* __restrict__ part, int nblk,
                                   IterScalars* __restrict__ sc) {
+  raise_wave_priority();
   if (threadIdx.x != 0) return;
   part += (int64_t)blockIdx.x * 2 * nblk;
   sc += blockIdx.x;
@@ -625,6 +654,7 @@ __global__ void dots_final_kernel(const double* __restrict__ part, int nblk,
 
 __global__ void normalize_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ v,
                                  IterScalars* __restrict__ sc, int last) {
+  raise_wave_priority();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   z += (int64_t)blockIdx.y * n;
   v += (int64_t)blockIdx.y * n;

@@ -334,8 +334,12 @@ struct MkArgs {
   const int64_t* rhs_off;   // per problem, bytes
 };
 
-// two workgroups (eight waves) per CU; the hi/lo products with more than 64 right-hand
-// sides keep one, so their accumulators fit in registers without spilling
+// row tiles per wave: four (each column fragment read from LDS feeds four row tiles), two
+// for the products with more than 64 right-hand sides.  Measured at the 2M-point, 64-column
+// shape: two row tiles at four waves per SIMD run 15% slower than four at two.
+constexpr int rt_of(int mode, int nq) { return (mode != MODE_F32V && nq > 4) ? 2 : 4; }
+// workgroups per CU the launch bounds ask for: two; the hi/lo products with more than 64
+// right-hand sides one, so that their accumulators fit in registers without spilling
 template <int MODE, int NQ>
 constexpr int mk_occupancy() { return (MODE == MODE_F16X3 && NQ > 4) ? 1 : 2; }
 
@@ -479,12 +483,16 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
     __syncthreads();
     int64_t T = T0;
     // pairs of tiles: on entry LDS buffer 0 holds tile T and s1 holds tile T + 1
+    // the empty asm statements keep each prefetch issued before the compute it overlaps
+    // (otherwise the scheduler may sink the loads below the LDS reads of the compute)
     for (; T + 1 < T1; T += 2) {
       s0 = gload(tc(T + 2));
+      asm volatile("" ::: "memory");
       compute(0);
       sstore(s1, 1);
       __syncthreads();
       s1 = gload(tc(T + 3));
+      asm volatile("" ::: "memory");
       compute(1);
       sstore(s0, 0);
       __syncthreads();
@@ -613,11 +621,12 @@ adasap_status_t disp_nq(const MkArgs& a, int nq, int grid, hipStream_t s) {
     else if (nq == 2) launch_mk<KS, KERN, MODE, 2, 4>(a, grid, s);
     else launch_mk<KS, KERN, MODE, 4, 4>(a, grid, s);
   } else {
+    constexpr int R4 = rt_of(MODE, 4);
     switch (nq) {
-      case 1: launch_mk<KS, KERN, MODE, 1, 4>(a, grid, s); break;
-      case 2: launch_mk<KS, KERN, MODE, 2, 4>(a, grid, s); break;
-      case 3: launch_mk<KS, KERN, MODE, 3, 4>(a, grid, s); break;
-      case 4: launch_mk<KS, KERN, MODE, 4, 4>(a, grid, s); break;
+      case 1: launch_mk<KS, KERN, MODE, 1, R4>(a, grid, s); break;
+      case 2: launch_mk<KS, KERN, MODE, 2, R4>(a, grid, s); break;
+      case 3: launch_mk<KS, KERN, MODE, 3, R4>(a, grid, s); break;
+      case 4: launch_mk<KS, KERN, MODE, 4, R4>(a, grid, s); break;
       case 5: launch_mk<KS, KERN, MODE, 5, 2>(a, grid, s); break;
       case 6: launch_mk<KS, KERN, MODE, 6, 2>(a, grid, s); break;
       case 7: launch_mk<KS, KERN, MODE, 7, 2>(a, grid, s); break;
@@ -690,15 +699,23 @@ struct RhsDesc {
 adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
                        const int64_t* ridx, int64_t m, int d, int kern, const RhsDesc& rd, int k,
                        void* out, DT ot, const KbEpilogue& ep, DevBuf& part, hipStream_t s,
-                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int ks_force = 0) {
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int ks_force = 0,
+                       int wg_cap = 0) {
   if (m <= 0) return ADASAP_OK;
-  const int RT = (rd.mode != MODE_F32V && rd.nq > 4) ? 2 : 4;
+  const int RT = rt_of(rd.mode, rd.nq);
   const int rows_per_wg = WAVES * RT * 16;
   const int rwg = (int)((m + rows_per_wg - 1) / rows_per_wg);
-  // aim for >= 2048 workgroups (8 per CU) when the column range allows it
-  int splits = (2048 + rwg - 1) / rwg;
-  if (splits > ntiles) splits = (int)(ntiles > 0 ? ntiles : 1);
-  if (splits >= 8) splits -= splits % 8;
+  int splits;
+  if (wg_cap > 0) {
+    // one resident round that leaves some workgroup slots free for a concurrent stream
+    splits = wg_cap / rwg;
+    if (splits > ntiles) splits = (int)(ntiles > 0 ? ntiles : 1);
+  } else {
+    // aim for >= 2048 workgroups (8 per CU) when the column range allows it
+    splits = (2048 + rwg - 1) / rwg;
+    if (splits > ntiles) splits = (int)(ntiles > 0 ? ntiles : 1);
+    if (splits >= 8) splits -= splits % 8;
+  }
   if (splits < 1) splits = 1;
   int64_t tps = (ntiles + splits - 1) / splits;
   if (tps < 1) tps = 1;
@@ -894,7 +911,7 @@ adasap_status_t mfma_product(const MfmaPack& pk, const int64_t* ridx, int64_t m,
   ADASAP_TRY(pack_rhs(R, rt, rows, k, k, nullptr, nt, mode, w.rhs, w.scale, w.tmp, rd, s));
   return mk_run(all_cols ? pk.cols.as<half8>() : static_cast<const half8*>(colsB), nt,
                 pk.rowv.as<half8>(), ridx, m, pk.d, pk.kern, rd, k, out, ot, ep, w.part, s, w.ev0,
-                w.ev1);
+                w.ev1, 0, w.wg_cap);
 }
 
 adasap_status_t mfma_product_packed(const MfmaPack& pk, const int64_t* ridx, int64_t m,
@@ -1066,7 +1083,7 @@ adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t*
     rd.p = w.rhs.p;
     rd.scale = w.scale.as<float>();
   }
-  const int RT = (rd.mode != MODE_F32V && rd.nq > 4) ? 2 : 4;
+  const int RT = rt_of(rd.mode, rd.nq);
   const int rows_per_wg = WAVES * RT * 16;
   const int rwg = (int)((b + rows_per_wg - 1) / rows_per_wg);
   int splits = (int)((2048 / P + rwg - 1) / rwg);

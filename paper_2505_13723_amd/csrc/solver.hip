@@ -78,8 +78,12 @@ struct adasap_handle_s {
   IterScalars* sc_host = nullptr;  // pinned trace of per-iteration scalars
   int64_t sc_host_cap = 0;
   std::vector<double> eta_tr, rho_tr, lh_tr;
-  std::vector<hipEvent_t> kev;  // event pairs around the step-I product kernel
+  // ring of event pairs around the step-I product kernel; a pair is read back (long after it
+  // completed) when the ring wraps, so no event is created inside the iteration loop
+  static constexpr int KEV_RING = 32;
+  std::vector<hipEvent_t> kev;
   int64_t kev_used = 0;
+  double step1_ms = 0;
   ~adasap_handle_s() {
     for (hipEvent_t e : kev) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -222,15 +226,23 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   const void* gp = at_w ? Wout : h->Z.p;
   const DT gt = at_w ? h->dtype : h->st;
   if (h->use_mfma) {
-    if ((int64_t)h->kev.size() < 2 * (h->kev_used + 1)) {
-      for (int e = 0; e < 2; ++e) {
+    const int ring = adasap_handle_s::KEV_RING;
+    if (h->kev.empty()) {
+      for (int e = 0; e < 2 * ring; ++e) {
         hipEvent_t ev;
         ADASAP_HIP(hipEventCreate(&ev));
         h->kev.push_back(ev);
       }
     }
-    h->mw.ev0 = h->kev[2 * h->kev_used];
-    h->mw.ev1 = h->kev[2 * h->kev_used + 1];
+    const int slot = (int)(h->kev_used % ring);
+    if (h->kev_used >= ring) {
+      float ms = 0;
+      ADASAP_HIP(hipEventSynchronize(h->kev[2 * slot + 1]));
+      ADASAP_HIP(hipEventElapsedTime(&ms, h->kev[2 * slot], h->kev[2 * slot + 1]));
+      h->step1_ms += ms;
+    }
+    h->mw.ev0 = h->kev[2 * slot];
+    h->mw.ev1 = h->kev[2 * slot + 1];
     ++h->kev_used;
     const adasap_status_t pst = block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s);
     h->mw.ev0 = h->mw.ev1 = nullptr;
@@ -561,6 +573,12 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   }
   if (hipMemsetAsync(h->scb.p, 0, sizeof(IterScalars), h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
   if (h->use_mfma) {
+    // the Step-I product runs as one resident round on 7/8 of the workgroup slots (two per
+    // CU), so that the second stream's sketch, Nystrom and powering kernels find room
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      h->mw.wg_cap = 2 * cus - cus / 4;
     st = mfma_pack_create(h->pack, n, d, k, X, h->dtype, cfg->kernel, cfg->lengthscale, h->s);
     if (st == ADASAP_ERR_UNSUPPORTED && cfg->precision == ADASAP_FP32) {
       h->use_mfma = false;  // coordinates outside the float16 range: vector-ALU products
@@ -608,6 +626,7 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
   ADASAP_TRY(convert(nk, W, h->dtype, h->Z.p, h->st, h->s));
   int64_t trace_pos = 0;
   h->kev_used = 0;
+  h->step1_ms = 0;
   double relres = -1, relmax = -1;
   ADASAP_TRY(run_sweep(h, 0, h->Y, h->dtype, W, rep.iters, relres, relmax, rep.solve_ms,
                        rep.check_ms, trace_pos));
@@ -658,9 +677,16 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
   }
   rep.relres = relres;
   rep.relres_maxcol = relmax;
-  for (int64_t i = 0; i < h->kev_used; ++i) {
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, h->kev[2 * i], h->kev[2 * i + 1]) == hipSuccess) rep.step1_kernel_ms += ms;
+  {
+    const int ring = adasap_handle_s::KEV_RING;
+    const int64_t pending = h->kev_used < ring ? h->kev_used : ring;
+    rep.step1_kernel_ms = h->step1_ms;
+    for (int64_t i = 0; i < pending; ++i) {
+      const int slot = (int)((h->kev_used - 1 - i) % ring);
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, h->kev[2 * slot], h->kev[2 * slot + 1]) == hipSuccess)
+        rep.step1_kernel_ms += ms;
+    }
   }
   rep.step1_launches = h->kev_used;
   if (report) *report = rep;
