@@ -24,8 +24,12 @@ solver, the network is trained on them, and a larger problem of the same field i
 to relative residual 1e-3 from zero and from the learned start (kept only if its residual
 after a one-pass probe beats the cold start's); `value` is the guarded time to residual.
 
+With --workload step1 it times the solver's Step-I launch alone (adasap_block_gradient on the
+2M-point, 64-column problem, K calls) and then copies a 1 GiB buffer once: the known-size
+transfer against which rocprofv3's FETCH_SIZE / WRITE_SIZE counters are calibrated.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-ttr] [--no-cpu]
-                       [--workload c3|batched|warm] [--ws-lam L] [--ws-n N]
+                       [--workload c3|batched|warm|step1] [--ws-lam L] [--ws-n N]
 """
 import argparse
 import json
@@ -59,7 +63,7 @@ def main():
     ap.add_argument("--ttr-passes", type=int, default=40, help="data passes allowed for time-to-residual")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=384)
-    ap.add_argument("--workload", choices=["c3", "batched", "warm"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "batched", "warm", "step1"], default="c3")
     ap.add_argument("--ws-lam", type=float, default=1.0, help="noise variance of the warm workload")
     ap.add_argument("--ws-n", type=int, default=1 << 20, help="points of the warm-start target")
     args = ap.parse_args()
@@ -75,6 +79,8 @@ def main():
         return bench_batched(args, torch, binding, inputs)
     if args.workload == "warm":
         return bench_warm(args, torch, binding, inputs)
+    if args.workload == "step1":
+        return bench_step1(args, torch, binding, inputs)
     cfgw = dict(inputs.WORKLOADS["c3_rbf_n2m_k64"])
     n, d, k = args.n, cfgw["d"], cfgw["k"]
     b, r, lam, ell = cfgw["b"], cfgw["r"], cfgw["lam"], cfgw["ell"]
@@ -220,6 +226,37 @@ def bench_batched(args, torch, binding, inputs):
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_step1(args, torch, binding, inputs):
+    """The Step-I product alone (the solver's launch), then a 1 GiB copy for calibration."""
+    w = inputs.WORKLOADS["c3_rbf_n2m_k64"]
+    lib = binding.load()
+    X, Y = inputs.make_c3(seed=w["seed"], n=w["n"], d=w["d"], k=w["k"], ell=w["ell"], lam=w["lam"],
+                          device="cuda")
+    h = lib.create(lib.config(kernel="rbf", lengthscale=w["ell"], lam=w["lam"], block_size=w["b"],
+                              rank=w["r"], seed=w["seed"], precision="mixed", max_iters=1), X, Y)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    Z = torch.randn(Y.shape, generator=g, device="cuda", dtype=torch.float32)
+    for t in range(args.warmup):
+        h.block_gradient(t, Z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        h.block_gradient(t, Z)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / max(1, args.steps) * 1e3
+    h.close()
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    a.clone()
+    torch.cuda.synchronize()
+    flops = float(w["b"]) * w["n"] * (2 * w["d"] + 2 * w["k"])
+    print(json.dumps({"metric": "Step-I launch (block gradient) wall time, n=2M d=11 k=64",
+                      "value": round(ms, 4), "unit": "ms", "steps": args.steps, "warmup": args.warmup,
+                      "higher_is_better": False, "gflops_per_s": round(flops / ms / 1e6, 1),
+                      "config": {"workload": "rbf_n2000000_d11_k64_step1", "b": w["b"]},
+                      "calibration_copy_bytes": 1 << 30}), flush=True)
 
 
 def bench_warm(args, torch, binding, inputs):

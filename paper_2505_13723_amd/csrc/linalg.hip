@@ -139,7 +139,9 @@ __global__ __launch_bounds__(256) void gramv_partial_kernel(int64_t rows, int p,
     for (int c = 0; c < q; ++c) part[((int64_t)blockIdx.x * p + col) * q + c] = acc[c] + red[col * 4 + c];
 }
 
-// OUT = f E + A M for a thin M (q <= 4): one wave per row of A (p <= 128 entries)
+// OUT = f E + A M for a thin M (q <= 4): 32 rows of A (p <= 128 entries) per workgroup, 8 per
+// wave with their loads in flight together (M staged in LDS once per workgroup)
+constexpr int GEMV_ROWS = 32;
 __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int q,
                                                         const double* __restrict__ A, int64_t lda,
                                                         const double* __restrict__ M,
@@ -158,26 +160,48 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int
   for (int e = threadIdx.x; e < p * q; e += 256) Ms[e] = M[e];
   __syncthreads();
   const int lane = threadIdx.x % 64;
-  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (row >= rows) return;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double f = 1.0;
+  if (alpha_mode == 1) f = 1.0 / *alpha_ptr;
+  else if (alpha_mode == 2) f = 1.0 / sqrt(*alpha_ptr);
+  // each wave takes 8 consecutive rows and issues their loads together
+  const int64_t rbase = (int64_t)blockIdx.x * GEMV_ROWS + (threadIdx.x / 64) * 8;
+  double acc[8][4];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[j][c] = 0.0;
   for (int l = lane; l < p; l += 64) {
-    const double a = A[row * lda + l];
+    double mv[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (c < q) acc[c] += a * Ms[l * q + c];
+    for (int c = 0; c < 4; ++c) mv[c] = c < q ? Ms[l * q + c] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t row = rbase + j;
+      const double a = row < rows ? A[row * lda + l] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[j][c] += a * mv[c];
+    }
   }
+  // (every index of acc is a compile-time constant, so the array stays in registers)
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
-    for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
-  if (lane == 0) {
-    double f = 1.0;
-    if (alpha_mode == 1) f = 1.0 / *alpha_ptr;
-    else if (alpha_mode == 2) f = 1.0 / sqrt(*alpha_ptr);
-    for (int c = 0; c < q; ++c) {
-      double v = acc[c];
-      if (E) v += f * E[row * lde + c];
-      out[row * ldo + c] = v;
+  for (int j = 0; j < 8; ++j) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c < q) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[j][c] += __shfl_xor(acc[j][c], off);
+      }
+    }
+    const int64_t row = rbase + j;
+    if (lane == 0 && row < rows) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c < q) {
+          double v = acc[j][c];
+          if (E) v += f * E[row * lde + c];
+          out[row * ldo + c] = v;
+        }
+      }
     }
   }
 }
@@ -494,7 +518,12 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
 
 // V = J_1 J_2 ... applied to the identity: ACC_ROWS rows of V per workgroup, one thread per
 // (row, pair); the rotations of one sweep are staged in LDS at a time.
-constexpr int ACC_ROWS = 4;
+constexpr int ACC_ROWS_MAX = 16;
+// threads per row of V: the rotation pairs (r/2), rounded up to 16, 32 or 64
+__host__ __device__ inline int acc_threads_per_row(int r) {
+  const int half = (r + 1) / 2;
+  return half <= 16 ? 16 : (half <= 32 ? 32 : 64);
+}
 __global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
                                                            const IterScalars* __restrict__ sc,
                                                            double* __restrict__ V, int64_t rot_cap) {
@@ -503,19 +532,21 @@ __global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* 
   sc += blockIdx.y;
   V += (int64_t)blockIdx.y * r * r;
   constexpr int ACC_STEPS = 32;  // rotation steps staged in LDS at a time
-  __shared__ double Vs[ACC_ROWS][RMAX];
+  __shared__ double Vs[ACC_ROWS_MAX][RMAX];
   __shared__ double R[ACC_STEPS * (RMAX / 2) * 2];
   const int tid = threadIdx.x;
   const int rp = r + (r & 1);
   const int half = rp / 2;
-  const int row0 = blockIdx.x * ACC_ROWS;
-  for (int e = tid; e < ACC_ROWS * RMAX; e += 256) {
+  const int tpr = acc_threads_per_row(r);  // threads per row: one per rotation pair
+  const int nrows = 256 / tpr;
+  const int row0 = blockIdx.x * nrows;
+  for (int e = tid; e < nrows * RMAX; e += 256) {
     const int a = e / RMAX, b = e % RMAX;
     Vs[a][b] = (row0 + a == b) ? 1.0 : 0.0;
   }
   const int sweeps = sc->sweeps;
   const int per_sweep = (rp - 1) * half;
-  const int ir = tid / 64, k = tid % 64;
+  const int ir = tid / tpr, k = tid % tpr;
   for (int sw = 0; sw < sweeps; ++sw) {
     for (int step = 0; step < rp - 1; ++step) {
       const int ls = step % ACC_STEPS;
@@ -542,7 +573,7 @@ __global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* 
     }
   }
   __syncthreads();
-  for (int e = tid; e < ACC_ROWS * r; e += 256) {
+  for (int e = tid; e < nrows * r; e += 256) {
     const int a = e / r, b = e % r;
     if (row0 + a < r) V[(int64_t)(row0 + a) * r + b] = Vs[a][b];
   }
@@ -729,7 +760,7 @@ adasap_status_t gemm_rm(int64_t rows, int p, int q, const double* A, const doubl
                         int alpha_mode, hipStream_t s, const Batch& bat) {
   if (rows <= 0) return ADASAP_OK;
   if (q <= 4 && p <= 128 && A2 == nullptr) {
-    hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)((rows + 3) / 4), bat.P), dim3(256), 0, s,
+    hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)((rows + GEMV_ROWS - 1) / GEMV_ROWS), bat.P), dim3(256), 0, s,
                        rows, p, q, A, lda, M, out, ldo, E, lde, alpha_ptr, alpha_mode, bat);
     ADASAP_LAUNCH_CHECK();
     return ADASAP_OK;
@@ -774,7 +805,8 @@ adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, dou
   const int64_t cap = (int64_t)jacobi_rot_capacity(r);
   hipLaunchKernelGGL(jacobi_kernel, dim3(P), dim3(1024), 0, s, r, H, evals, rot_buf, sc, cap);
   ADASAP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_ROWS - 1) / ACC_ROWS, P), dim3(256), 0, s,
+  const int acc_rows = 256 / acc_threads_per_row(r);
+  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + acc_rows - 1) / acc_rows, P), dim3(256), 0, s,
                      r, rot_buf, sc, V, cap);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;

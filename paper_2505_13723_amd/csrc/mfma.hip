@@ -22,6 +22,7 @@
 //   MODE_F32V  K in float32 times float32 R on the vector ALUs (k <= 4)
 // The column range is split over workgroups; partial sums are added in a fixed order.
 #include <cmath>
+#include <type_traits>
 
 #include "mfma.h"
 #include "kfun.h"
@@ -43,17 +44,27 @@ __device__ inline f4 mfma16(half8 a, half8 b, f4 c) {
 }
 
 // ---------------------------------------------------------------- packing
-__global__ void mean_partial_kernel(const void* __restrict__ X, DT xt, int64_t n, int d,
-                                    double* __restrict__ part) {
-  // block b sums rows [b*4096, ...) for every coordinate (thread f < d)
+__global__ __launch_bounds__(256) void mean_partial_kernel(const void* __restrict__ X, DT xt,
+                                                           int64_t n, int d,
+                                                           double* __restrict__ part) {
+  // block b sums rows [b*4096, ...): thread t takes coordinate t % d of rows t / d, t / d + 256 / d,
+  // ...; the row groups are then added in a fixed order
+  __shared__ double red[256];
   const int64_t r0 = (int64_t)blockIdx.x * 4096;
   const int64_t r1 = r0 + 4096 < n ? r0 + 4096 : n;
-  for (int f = threadIdx.x; f < d; f += blockDim.x) {
-    double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r)
+  const int tid = threadIdx.x;
+  const int rstep = 256 / d, f = tid % d, rg = tid / d;
+  double s = 0.0;
+  if (rg < rstep)
+    for (int64_t r = r0 + rg; r < r1; r += rstep)
       s += xt == DT::F64 ? static_cast<const double*>(X)[r * d + f]
                          : (double)static_cast<const float*>(X)[r * d + f];
-    part[(int64_t)blockIdx.x * d + f] = s;
+  red[tid] = s;
+  __syncthreads();
+  if (tid < d) {
+    double t = 0.0;
+    for (int g = 0; g < rstep; ++g) t += red[g * d + tid];
+    part[(int64_t)blockIdx.x * d + tid] = t;
   }
 }
 
@@ -343,6 +354,17 @@ constexpr int rt_of(int mode, int nq) { return (mode != MODE_F32V && nq > 4) ? 2
 template <int MODE, int NQ>
 constexpr int mk_occupancy() { return (MODE == MODE_F16X3 && NQ > 4) ? 1 : 2; }
 
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): indices stay
+// compile-time constants (a #pragma unroll loop over a register array can be left rolled,
+// which moves the array to scratch memory)
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (N > 0) {
+    static_for<N - 1>(f);
+    f(std::integral_constant<int, N - 1>{});
+  }
+}
+
 template <int KS, int MODE, int NQ>
 struct MkShape {
   static constexpr int A_FR = 2 * KS * 64;                                            // half8 per tile
@@ -405,18 +427,20 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
     Stage st;
     const uint4* ca = reinterpret_cast<const uint4*>(colA_p) + T * A_FR;
     const uint4* rb = reinterpret_cast<const uint4*>(rhs_p) + T * (R_FR + (R_F32 * 4) / 16);
-#pragma unroll
-    for (int u = 0; u < LOADS16; ++u) {
+    static_for<LOADS16>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
       const int e = tid + u * 256;
       const uint4* src = e < A_FR ? ca + e : (e < TOTAL16 ? rb + (e - A_FR) : ca);
       st.v[u] = *src;
-    }
+    });
     return st;
   };
   auto sstore = [&](const Stage& st, int buf) __attribute__((always_inline)) {
     uint4* dst = reinterpret_cast<uint4*>(lds + buf * BUF_BYTES);
-#pragma unroll
-    for (int u = 0; u < LOADS16; ++u) dst[tid + u * 256] = st.v[u];
+    static_for<LOADS16>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      dst[tid + u * 256] = st.v[u];
+    });
   };
   auto compute = [&](int buf) __attribute__((always_inline)) {
     const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
@@ -862,7 +886,7 @@ adasap_status_t mfma_pack_create(MfmaPack& pk, int64_t n, int d, int k, const vo
   ADASAP_TRY(pk.flag.ensure(sizeof(int)));
   const int nblk = (int)((n + 4095) / 4096);
   ADASAP_TRY(pk.tmp.ensure((size_t)(nblk > 0 ? nblk : 1) * d * sizeof(double)));
-  hipLaunchKernelGGL(mean_partial_kernel, dim3(nblk), dim3(64), 0, s, X, xt, n, d, pk.tmp.as<double>());
+  hipLaunchKernelGGL(mean_partial_kernel, dim3(nblk), dim3(256), 0, s, X, xt, n, d, pk.tmp.as<double>());
   ADASAP_LAUNCH_CHECK();
   hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64), 0, s, pk.tmp.as<double>(), nblk, d, n,
                      pk.centre.as<double>());
@@ -1005,7 +1029,7 @@ adasap_status_t mfma_batch_pack_create(MfmaBatchPack& bp, int P, const int64_t* 
   for (int p = 0; p < P; ++p) {
     const int nblk = (int)((n[p] + 4095) / 4096);
     ADASAP_TRY(tmp.ensure((size_t)nblk * d[p] * sizeof(double)));
-    hipLaunchKernelGGL(mean_partial_kernel, dim3(nblk), dim3(64), 0, s, X[p], xt, n[p], d[p],
+    hipLaunchKernelGGL(mean_partial_kernel, dim3(nblk), dim3(256), 0, s, X[p], xt, n[p], d[p],
                        tmp.as<double>());
     hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64), 0, s, tmp.as<double>(), nblk, d[p],
                        n[p], bp.centre.as<double>());
