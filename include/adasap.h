@@ -100,9 +100,9 @@ typedef struct {
   int32_t not_pd_events;   /* Nystrom cores that needed a shift increase */
   int32_t status;          /* adasap_status_t of the solve */
   double step1_kernel_ms;  /* device time of the step-I kernel-block product kernels (matrix-core path) */
-  int64_t step1_launches;  /* number of those launches */
+  int64_t step1_launches;  /* number of those launches (batched solves: the rounds run eagerly) */
   int32_t jacobi_sweeps_max; /* most sweeps one Nystrom eigendecomposition needed */
-  int32_t reserved;
+  int32_t reserved;        /* batched solves: column tiles per work item chosen by the autotuner */
 } adasap_report_t;
 
 typedef struct adasap_handle_s* adasap_handle_t;
@@ -174,6 +174,10 @@ typedef struct {
  * preconditioner, accelerated steps with the gradient at Z, k = 1, 1 <= d <= 16 and n >= b
  * for every problem.  When tol > 0 or check_every > 0 each problem's final relative residual
  * is computed.  `reports` (host, count entries, may be NULL) receives per-problem statistics.
+ * Execution: the host draws round t + 1's blocks while the device runs round t; the first
+ * round times the step-I launch for work items of 16, 32, 64 and 128 column tiles and keeps
+ * the fastest; every round but the first and the last replays one captured hipGraph of the
+ * round's device work (the iteration counter reaches it through device memory).
  * Synchronises the stream. */
 adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int32_t count,
                                    const adasap_config_t* cfg, int32_t dtype, void* stream,

@@ -124,7 +124,7 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
   ADASAP_TRY(Yp.ensure(R * 4));
   ADASAP_TRY(rowp.ensure(R * 4));
   ADASAP_TRY(dcoef.ensure(coefs.size() * 8));
-  ADASAP_TRY(Bdev.ensure(Pb * 8));
+  ADASAP_TRY(Bdev.ensure((Pb + 1) * 8));
   ADASAP_TRY(G.ensure(Pb * 8));
   ADASAP_TRY(D.ensure(Pb * 8));
   ADASAP_TRY(Om.ensure(Pbr * 8));
@@ -170,25 +170,27 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     ADASAP_LAUNCH_CHECK();
   }
   hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, e0 = nullptr, e1 = nullptr, k0 = nullptr, k1 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, k0 = nullptr, k1 = nullptr;
   ADASAP_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
   ADASAP_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
   ADASAP_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
-  ADASAP_HIP(hipEventCreate(&e0));
-  ADASAP_HIP(hipEventCreate(&e1));
   ADASAP_HIP(hipEventCreate(&k0));
   ADASAP_HIP(hipEventCreate(&k1));
   struct Cleanup {
     hipStream_t s2;
-    hipEvent_t e[6];
+    hipEvent_t e[4];
     ~Cleanup() {
       if (s2) (void)hipStreamSynchronize(s2), (void)hipStreamDestroy(s2);
       for (hipEvent_t x : e)
         if (x) (void)hipEventDestroy(x);
     }
-  } cleanup{s2, {ev_fork, ev_join, e0, e1, k0, k1}};
+  } cleanup{s2, {ev_fork, ev_join, k0, k1}};
+  // two pinned upload slots of Pb + 1 entries: every problem's block, then the iteration
+  // counter t (read on the device by the random-number kernels, so that a captured round
+  // replays with the current t)
+  const size_t slot_len = Pb + 1;
   int64_t* Bhost = nullptr;
-  if (hipHostMalloc((void**)&Bhost, Pb * sizeof(int64_t)) != hipSuccess) {
+  if (hipHostMalloc((void**)&Bhost, 2 * slot_len * sizeof(int64_t)) != hipSuccess) {
     set_error("pinned host allocation failed");
     return ADASAP_ERR_OOM;
   }
@@ -206,25 +208,50 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
   const double eps = std::ldexp(1.0, -23);
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   double solve_ms = 0, step1_ms = 0;
+  int step1_timed = 0;
   const int64_t Tmax = cfg->max_iters;
   Batch bBR{P, (int64_t)b * r, (int64_t)b * r, (int64_t)r * r, 0, 0};  // P x b x r Gram operands
-  for (int64_t t = 0; t < Tmax; ++t) {
-    // host: every problem's block, drawn in parallel, as global row indices
-    ADASAP_HIP(hipStreamSynchronize(s));  // the pinned buffer of the previous upload is free
-    {
-      std::vector<std::thread> pool;
-      for (unsigned th = 0; th < nthreads; ++th)
-        pool.emplace_back([&, th]() {
-          for (int p = (int)th; p < P; p += (int)nthreads) {
-            int64_t* Bp = Bhost + (size_t)p * b;
-            sample_block_host(cfg->seed + (uint64_t)p, PURPOSE_B, (uint64_t)t, n[p], b, Bp);
-            for (int64_t i = 0; i < b; ++i) Bp[i] += bp.row_off[p];
-          }
-        });
-      for (auto& th : pool) th.join();
+  const int64_t* t_dev = Bdev.as<int64_t>() + Pb;
+  // events: upload slots, and a ring of per-round timing pairs read back when the ring wraps
+  constexpr int RING = 16;
+  std::vector<hipEvent_t> slot_ev(2, nullptr), rev(2 * RING, nullptr);
+  struct EvFree {
+    std::vector<hipEvent_t>* a;
+    std::vector<hipEvent_t>* b;
+    ~EvFree() {
+      for (hipEvent_t e : *a)
+        if (e) (void)hipEventDestroy(e);
+      for (hipEvent_t e : *b)
+        if (e) (void)hipEventDestroy(e);
     }
-    ADASAP_HIP(hipEventRecord(e0, s));
-    ADASAP_HIP(hipMemcpyAsync(Bdev.p, Bhost, Pb * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  } evfree{&slot_ev, &rev};
+  for (auto& e : slot_ev) ADASAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : rev) ADASAP_HIP(hipEventCreate(&e));
+  auto take_round_time = [&](int64_t u) -> adasap_status_t {
+    const int i = (int)(u % RING);
+    float ms = 0;
+    ADASAP_HIP(hipEventSynchronize(rev[2 * i + 1]));
+    ADASAP_HIP(hipEventElapsedTime(&ms, rev[2 * i], rev[2 * i + 1]));
+    solve_ms += ms;
+    return ADASAP_OK;
+  };
+  // a captured round (graph) replays every round but the first (eager: it sizes the scratch
+  // buffers and runs the autotuner) and the last (eager: it also writes W)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool use_graph = true;
+  struct GraphFree {
+    hipGraph_t* g;
+    hipGraphExec_t* x;
+    ~GraphFree() {
+      if (*x) (void)hipGraphExecDestroy(*x);
+      if (*g) (void)hipGraphDestroy(*g);
+    }
+  } graphfree{&graph, &graph_exec};
+  int chosen_chunk = 64;
+
+  // the device work of one round (B_t and t already uploaded); `last` also writes W
+  auto round = [&](bool last, bool timed) -> adasap_status_t {
     const int64_t* B = Bdev.as<int64_t>();
     ADASAP_HIP(hipEventRecord(ev_fork, s));
     ADASAP_HIP(hipStreamWaitEvent(s2, ev_fork, 0));
@@ -241,10 +268,11 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     epg.lde2 = 1;
     epg.a2 = -1.0;
     epg.bsIdx = b;
-    ADASAP_TRY(mfma_batch_stepI(bp, q, B, b, Z.as<float>(), G.as<double>(), epg, w1, s, k0, k1));
+    ADASAP_TRY(mfma_batch_stepI(bp, q, B, b, Z.as<float>(), G.as<double>(), epg, w1, s,
+                                timed ? k0 : nullptr, timed ? k1 : nullptr));
     // second stream: sketch, Nystrom factors, step size for every problem
     ADASAP_TRY(mfma_batch_pack_blocks(bp, B, b, colsB, s2));
-    ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_OMEGA, (uint64_t)t, b * r, Om.as<double>(), s2, P));
+    ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_OMEGA, 0, b * r, Om.as<double>(), s2, P, t_dev));
     KbEpilogue none;
     ADASAP_TRY(mfma_batch_block_product(bp, B, b, colsB.p, Om.as<double>(), r, mfma_mode_f16x3(),
                                         Ysk.as<double>(), none, w2, s2));
@@ -274,7 +302,7 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     double* wv = ww.as<double>();
     double* u = uu.as<double>();
     double* z = zz.as<double>();
-    ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_POW, (uint64_t)t, b, v, s2, P));
+    ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_POW, 0, b, v, s2, P, t_dev));
     ADASAP_TRY(normalize_inplace(b, v, sc, pd, s2, P));
     for (int i = 0; i < cfg->power_iters; ++i) {
       ADASAP_TRY(isqrt(v, wv));
@@ -297,19 +325,89 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     ADASAP_TRY(gemm_rm(b, r, 1, U.as<double>(), nullptr, nullptr, r, coef.as<double>(), D.as<double>(),
                        1, G.as<double>(), 1, &sc->rho, 1, s,
                        Batch{P, (int64_t)b * r, (int64_t)r, (int64_t)b, (int64_t)b, SC_DOUBLES}));
-    const bool last = t + 1 == Tmax;
     ADASAP_TRY(nesterov_dense(R, V.p, Z.p, DT::F32, nc, last ? Wp.p : nullptr, DT::F32, s,
                               rowp.as<int32_t>(), dcoef.as<double>(), 1));
     ADASAP_TRY(nesterov_sparse(b, 1, B, D.as<double>(), V.p, Z.p, DT::F32, nc, sc,
                                last ? Wp.p : nullptr, DT::F32, s, P, dcoef.as<double>()));
-    ADASAP_HIP(hipEventRecord(e1, s));
-    ADASAP_HIP(hipEventSynchronize(e1));
-    float ms = 0, kms = 0;
-    ADASAP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    ADASAP_HIP(hipEventElapsedTime(&kms, k0, k1));
-    solve_ms += ms;
-    step1_ms += kms;
+    return ADASAP_OK;
+  };
+
+  for (int64_t t = 0; t < Tmax; ++t) {
+    const int slot = (int)(t & 1);
+    int64_t* Bs = Bhost + slot * slot_len;
+    // the upload that last read this slot (round t - 2) has completed
+    ADASAP_HIP(hipEventSynchronize(slot_ev[slot]));
+    // host: every problem's block, drawn in parallel, as global row indices
+    {
+      std::vector<std::thread> pool;
+      for (unsigned th = 0; th < nthreads; ++th)
+        pool.emplace_back([&, th]() {
+          for (int p = (int)th; p < P; p += (int)nthreads) {
+            int64_t* Bp = Bs + (size_t)p * b;
+            sample_block_host(cfg->seed + (uint64_t)p, PURPOSE_B, (uint64_t)t, n[p], b, Bp);
+            for (int64_t i = 0; i < b; ++i) Bp[i] += bp.row_off[p];
+          }
+        });
+      for (auto& th : pool) th.join();
+    }
+    Bs[Pb] = t;
+    if (t >= RING) ADASAP_TRY(take_round_time(t - RING));
+    ADASAP_HIP(hipEventRecord(rev[2 * (t % RING)], s));
+    ADASAP_HIP(hipMemcpyAsync(Bdev.p, Bs, slot_len * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    ADASAP_HIP(hipEventRecord(slot_ev[slot], s));
+    const bool last = t + 1 == Tmax;
+    if (t == 0) {
+      // autotuner: time the step-I launch for a few work-item sizes on this batch, keep the fastest
+      const int cands[4] = {16, 32, 64, 128};
+      float best = 1e30f;
+      KbEpilogue none;
+      for (int ci = 0; ci < 4; ++ci) {
+        MfmaQueue qc;
+        ADASAP_TRY(mfma_batch_queue_create(bp, b, cands[ci], qc, s));
+        float ms = 0;
+        for (int rep = 0; rep < 2; ++rep) {  // the first launch warms caches and allocations
+          ADASAP_TRY(mfma_batch_stepI(bp, qc, Bdev.as<int64_t>(), b, Z.as<float>(), G.as<double>(),
+                                      none, w1, s, k0, k1));
+          ADASAP_HIP(hipEventSynchronize(k1));
+          ADASAP_HIP(hipEventElapsedTime(&ms, k0, k1));
+        }
+        if (ms < best) {
+          best = ms;
+          chosen_chunk = cands[ci];
+        }
+      }
+      if (chosen_chunk != 64) ADASAP_TRY(mfma_batch_queue_create(bp, b, chosen_chunk, q, s));
+    }
+    if (t >= 1 && !last && use_graph) {
+      if (!graph_exec) {
+        // capture this round's device work once; any capture failure leaves the eager rounds
+        hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+        adasap_status_t rst = ce == hipSuccess ? round(false, false) : ADASAP_ERR_DEVICE;
+        hipGraph_t g = nullptr;
+        const hipError_t ee = ce == hipSuccess ? hipStreamEndCapture(s, &g) : ce;
+        if (rst == ADASAP_OK && ee == hipSuccess && g &&
+            hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0) == hipSuccess) {
+          graph = g;
+        } else {
+          if (g) (void)hipGraphDestroy(g);
+          graph_exec = nullptr;
+          use_graph = false;
+          (void)hipGetLastError();
+        }
+      }
+      if (use_graph) ADASAP_HIP(hipGraphLaunch(graph_exec, s));
+      else ADASAP_TRY(round(false, false));
+    } else {
+      ADASAP_TRY(round(last, true));
+      float kms = 0;
+      ADASAP_HIP(hipEventSynchronize(k1));
+      ADASAP_HIP(hipEventElapsedTime(&kms, k0, k1));
+      step1_ms += kms;
+      ++step1_timed;
+    }
+    ADASAP_HIP(hipEventRecord(rev[2 * (t % RING) + 1], s));
   }
+  for (int64_t u = Tmax > RING ? Tmax - RING : 0; u < Tmax; ++u) ADASAP_TRY(take_round_time(u));
   // results back to the callers' buffers, per-problem residuals and scalars
   std::vector<IterScalars> hs(P);
   ADASAP_HIP(hipMemcpyAsync(hs.data(), scb.p, (size_t)P * sizeof(IterScalars), hipMemcpyDeviceToHost, s));
@@ -326,7 +424,8 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     rep.iters = Tmax;
     rep.solve_ms = solve_ms;
     rep.step1_kernel_ms = step1_ms;
-    rep.step1_launches = Tmax;
+    rep.step1_launches = step1_timed;
+    rep.reserved = chosen_chunk;
     rep.eta_last = hs[p].eta;
     rep.rho_last = hs[p].rho;
     rep.lambda_hat_last = hs[p].lam_hat;

@@ -118,8 +118,9 @@ adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf&
 
 // ---- random numbers (rng.hip) -------------------------------------------------------------
 // Batched over P problems: problem p uses seed + p and writes out + p * count.
+// If t_dev is set, the stream counter is read from device memory (*t_dev) instead of t.
 adasap_status_t normals_dev(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
-                            double* out, hipStream_t s, int P = 1);
+                            double* out, hipStream_t s, int P = 1, const int64_t* t_dev = nullptr);
 void sample_block_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n, int64_t b,
                        int64_t* out);
 // uniform permutation of [0, m) (Fisher-Yates on the stream (seed, purpose, t))

@@ -16,8 +16,9 @@ namespace {
 
 // one Philox block gives the four words 4i..4i+3 = normals 2i and 2i+1
 __global__ void normals_kernel(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
-                               double* __restrict__ out) {
+                               double* __restrict__ out, const int64_t* __restrict__ t_dev) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t_dev) t = (uint64_t)*t_dev;  // counter read from device memory (replayable launches)
   seed += blockIdx.y;  // problem p of a batch draws with seed + p
   out += (int64_t)blockIdx.y * count;
   if (2 * i >= count) return;
@@ -66,11 +67,11 @@ uint64_t bounded(HostStream& hs, uint64_t s) {
 }  // namespace
 
 adasap_status_t normals_dev(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
-                            double* out, hipStream_t s, int P) {
+                            double* out, hipStream_t s, int P, const int64_t* t_dev) {
   if (count <= 0) return ADASAP_OK;
   const int64_t blocks = (count + 1) / 2;
   hipLaunchKernelGGL(normals_kernel, dim3((unsigned)((blocks + 255) / 256), P), dim3(256), 0, s,
-                     seed, purpose, t, count, out);
+                     seed, purpose, t, count, out, t_dev);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
