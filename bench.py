@@ -47,6 +47,10 @@ METRIC = "time to rel. residual 1e-3 (s) & kernel-block GFLOP/s, n=2M d=11, 1 GP
 PEAK_F16_MFMA_TFLOPS = 2500.0
 # transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 8 lanes per clock x 2.4 GHz
 PEAK_EXP_TPS = 256 * 4 * 8 * 2.4e9 / 1e12
+# HBM bytes of one Step-I launch at the 2M-point, 64-column shape: rocprofv3 FETCH_SIZE +
+# WRITE_SIZE of the launch (2.009e6 + 2.867e4 KiB), each scaled by 1.0486, the ratio of true to
+# counted bytes for a 1 GiB copy (profiles/mk_kernel_rbf_n2m_d11_k64.md)
+STEP1_TRAFFIC_BYTES_N2M = 2.19e9
 
 
 def log(msg):
@@ -155,7 +159,8 @@ def main():
         "time_to_relres_1e-3": ttr,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 1),
                      "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_F16_MFMA_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_F16_MFMA_TFLOPS, 4),
+                     "traffic": STEP1_TRAFFIC_BYTES_N2M if n == 2_000_000 else None,
                      "kernel": "mk_kernel (step-I kernel-block product)",
                      "kernel_ms": round(kern_ms, 4),
                      "algorithmic_flops_per_launch": flops_step1},
