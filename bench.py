@@ -28,8 +28,15 @@ With --workload step1 it times the solver's Step-I launch alone (adasap_block_gr
 2M-point, 64-column problem, K calls) and then copies a 1 GiB buffer once: the known-size
 transfer against which rocprofv3's FETCH_SIZE / WRITE_SIZE counters are calibrated.
 
+With --workload matern32_n1m (Matern-3/2, n = 1M, d = 11 with 5% clustered near-duplicates,
+lambda = 1e-3, b = 8192, r = 100, FP32) or --workload rbf_n100m (RBF, n = 1e8, d = 9,
+lambda = 1e-2, b = 32768, r = 128, FP32) it times K iterations of that single problem; the
+first also runs to relative residual 1e-3 (checked once per pass), the second reports the
+row-subsampled residual estimate (2^17 rows) after its K iterations.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-ttr] [--no-cpu]
-                       [--workload c3|batched|warm|step1] [--ws-lam L] [--ws-n N]
+                       [--workload c3|batched|warm|step1|matern32_n1m|rbf_n100m]
+                       [--ws-lam L] [--ws-n N]
 """
 import argparse
 import json
@@ -67,7 +74,10 @@ def main():
     ap.add_argument("--ttr-passes", type=int, default=40, help="data passes allowed for time-to-residual")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=384)
-    ap.add_argument("--workload", choices=["c3", "batched", "warm", "step1"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "batched", "warm", "step1", "matern32_n1m", "rbf_n100m"],
+                    default="c3")
+    ap.add_argument("--shape", choices=["rbf_n2m_k64", "rbf_n100m"], default="rbf_n2m_k64",
+                    help="problem of the step1 workload")
     ap.add_argument("--ws-lam", type=float, default=1.0, help="noise variance of the warm workload")
     ap.add_argument("--ws-n", type=int, default=1 << 20, help="points of the warm-start target")
     args = ap.parse_args()
@@ -85,6 +95,8 @@ def main():
         return bench_warm(args, torch, binding, inputs)
     if args.workload == "step1":
         return bench_step1(args, torch, binding, inputs)
+    if args.workload in ("matern32_n1m", "rbf_n100m"):
+        return bench_single_k1(args, torch, binding, inputs)
     cfgw = dict(inputs.WORKLOADS["c3_rbf_n2m_k64"])
     n, d, k = args.n, cfgw["d"], cfgw["k"]
     b, r, lam, ell = cfgw["b"], cfgw["r"], cfgw["lam"], cfgw["ell"]
@@ -233,14 +245,99 @@ def bench_batched(args, torch, binding, inputs):
     print(json.dumps(line), flush=True)
 
 
+def bench_single_k1(args, torch, binding, inputs):
+    """One right-hand side, FP32: the ill-conditioned Matern-3/2 problem or the 1e8-point one."""
+    big = args.workload == "rbf_n100m"
+    w = inputs.WORKLOADS["c5_rbf_n100m" if big else "c2_matern32_n1m"]
+    lib = binding.load()
+    n, d, b, r, lam, ell = w["n"], w["d"], w["b"], w["r"], w["lam"], w["ell"]
+    log("generating inputs n=%d d=%d on the GPU" % (n, d))
+    if big:
+        X, y = inputs.make_c5(seed=w["seed"], n=n, d=d, ell=ell, lam=lam, device="cuda", chunk=1 << 18)
+    else:
+        X, y = inputs.make_c2(seed=w["seed"], n=n, d=d, ell=ell, lam=lam, device="cuda")
+    Y = y[:, None].contiguous()
+    del y
+    torch.cuda.synchronize()
+
+    def make(iters, tol=0.0, check_every=0):
+        c = lib.config(kernel=w["kernel"], lengthscale=ell, lam=lam, block_size=b, rank=r,
+                       max_iters=iters, tol=tol, check_every=check_every, seed=w["seed"],
+                       precision="fp32")
+        return lib.create(c, X, Y)
+
+    W = torch.zeros_like(Y)
+    if args.warmup > 0:
+        h = make(args.warmup)
+        h.solve(W)
+        h.close()
+    h = make(args.steps)
+    W.zero_()
+    torch.cuda.synchronize()
+    rep = h.solve(W)
+    ms_per_step = rep["solve_ms"] / max(1, rep["iters"])
+    kern_ms = rep["step1_kernel_ms"] / max(1, rep["step1_launches"])
+    pairs = float(b) * n
+    trans = 1 if w["kernel"] == "rbf" else 2  # exp2, or sqrt and exp2 (Matern)
+    achieved = pairs * trans / (kern_ms * 1e-3) / 1e12
+    value = pairs * (2 * d + 2) / (ms_per_step * 1e-3) / 1e9
+    extra = {}
+    if big:
+        m = 1 << 17
+        t0 = time.perf_counter()
+        est, worst = h.residual_rows(W, m, 12)
+        extra["relres_subsampled"] = {"rows": m, "estimate": est, "after_iterations": rep["iters"],
+                                      "seconds": round(time.perf_counter() - t0, 3)}
+    h.close()
+    log("steps=%d solve_ms=%.1f (%.3f ms/step), step-I kernel %.3f ms" % (rep["iters"], rep["solve_ms"],
+                                                                       ms_per_step, kern_ms))
+    if not big and not args.no_ttr:
+        per_pass = int(math.ceil(n / b))
+        h = make(per_pass * args.ttr_passes, tol=1e-3, check_every=per_pass)
+        W.zero_()
+        rep2 = h.solve(W)
+        h.close()
+        reached = 0 <= rep2["relres"] <= 1e-3
+        extra["time_to_relres_1e-3"] = {"seconds": rep2["solve_ms"] / 1e3 if reached else None,
+                                        "reached": bool(reached), "iterations": rep2["iters"],
+                                        "passes": rep2["iters"] / per_pass, "relres": rep2["relres"],
+                                        "check_seconds_off_clock": rep2["check_ms"] / 1e3}
+        log("time-to-residual: %s" % json.dumps(extra["time_to_relres_1e-3"]))
+    line = {
+        "metric": "kernel-block GFLOP/s (Step-I flops per whole iteration), %s, 1 GPU" % args.workload,
+        "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": rep["iters"],
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f16 hi/lo matrix-core distances, f32 vector K.Z), f64 Nystrom core",
+        "data": "synthetic (seeded, GP prior-draw targets)",
+        "config": {"workload": "%s_n%d_d%d" % (w["kernel"], n, d), "n": n, "d": d, "b": b, "r": r,
+                   "lambda": lam, "lengthscale": ell, "kernel": w["kernel"], "precision": "fp32"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
+                     "unit": "Ttranscendental/s", "frac": round(achieved / PEAK_EXP_TPS, 4),
+                     "traffic": None, "kernel": "mk_kernel (Step-I product, float32 vector mode)",
+                     "kernel_ms": round(kern_ms, 4)},
+        "cpu_baseline": None,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
 def bench_step1(args, torch, binding, inputs):
     """The Step-I product alone (the solver's launch), then a 1 GiB copy for calibration."""
-    w = inputs.WORKLOADS["c3_rbf_n2m_k64"]
     lib = binding.load()
-    X, Y = inputs.make_c3(seed=w["seed"], n=w["n"], d=w["d"], k=w["k"], ell=w["ell"], lam=w["lam"],
-                          device="cuda")
+    if args.shape == "rbf_n100m":
+        w = dict(inputs.WORKLOADS["c5_rbf_n100m"], k=1)
+        X, y = inputs.make_c5(seed=w["seed"], n=w["n"], d=w["d"], ell=w["ell"], lam=w["lam"],
+                              device="cuda", chunk=1 << 18)
+        Y = y[:, None].contiguous()
+        prec = "fp32"
+    else:
+        w = inputs.WORKLOADS["c3_rbf_n2m_k64"]
+        X, Y = inputs.make_c3(seed=w["seed"], n=w["n"], d=w["d"], k=w["k"], ell=w["ell"],
+                              lam=w["lam"], device="cuda")
+        prec = "mixed"
     h = lib.create(lib.config(kernel="rbf", lengthscale=w["ell"], lam=w["lam"], block_size=w["b"],
-                              rank=w["r"], seed=w["seed"], precision="mixed", max_iters=1), X, Y)
+                              rank=w["r"], seed=w["seed"], precision=prec, max_iters=1), X, Y)
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
     Z = torch.randn(Y.shape, generator=g, device="cuda", dtype=torch.float32)
@@ -257,10 +354,11 @@ def bench_step1(args, torch, binding, inputs):
     a.clone()
     torch.cuda.synchronize()
     flops = float(w["b"]) * w["n"] * (2 * w["d"] + 2 * w["k"])
-    print(json.dumps({"metric": "Step-I launch (block gradient) wall time, n=2M d=11 k=64",
+    print(json.dumps({"metric": "Step-I launch (block gradient) wall time",
                       "value": round(ms, 4), "unit": "ms", "steps": args.steps, "warmup": args.warmup,
                       "higher_is_better": False, "gflops_per_s": round(flops / ms / 1e6, 1),
-                      "config": {"workload": "rbf_n2000000_d11_k64_step1", "b": w["b"]},
+                      "config": {"workload": "rbf_n%d_d%d_k%d_step1" % (w["n"], w["d"], w["k"]),
+                                 "b": w["b"]},
                       "calibration_copy_bytes": 1 << 30}), flush=True)
 
 

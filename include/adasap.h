@@ -138,6 +138,15 @@ adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, cons
 adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres,
                                 double* relres_maxcol);
 
+/* Row-subsampled estimate of the relative residual, for problems where the full product
+ * (n^2 pairs) is too large: m rows S, a uniform m-subset of [0, n) (Floyd, Philox stream
+ * (seed, 12, 0), ascending), give sqrt(sum_{i in S} |r_i|^2 / sum_{i in S} |y_i|^2) with
+ * r = (K + lambda I) W - Y, each row computed against all n columns with the residual's
+ * kernels (float16 hi/lo products or float64) and float64 sums.  relres, relres_maxcol
+ * (host) may be NULL; rows_out (device int64[m]) may be NULL.  Synchronises the stream. */
+adasap_status_t adasap_residual_rows(adasap_handle_t h, const void* W, int64_t m, uint64_t seed,
+                                     double* relres, double* relres_maxcol, int64_t* rows_out);
+
 /* The block gradient of Step I of Alg. 2 at a caller-given point:
  * G = K(X_B, X) Z + lambda Z[B] - Y[B], where B = B_t is the block adasap_solve samples at
  * iteration t (sorted, from the handle's seed), computed with the same kernels, precision

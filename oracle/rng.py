@@ -42,6 +42,8 @@ PURPOSE_OMEGA = 6
 PURPOSE_POW = 7
 # minibatch order of the warm-start network's training, epoch e = counter t
 PURPOSE_MINIBATCH = 11
+# rows of a subsampled residual estimate
+PURPOSE_RESROWS = 12
 # refinement sweep s draws with purpose + PURPOSE_SWEEP_STRIDE * s
 PURPOSE_SWEEP_STRIDE = 16
 

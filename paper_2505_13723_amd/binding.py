@@ -88,6 +88,7 @@ _SIGNATURES = {
     "adasap_residual": (_I32, [_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "adasap_get_trace": (_I32, [_P, _P, _P, _P, _I64]),
     "adasap_block_gradient": (_I32, [_P, _I64, _P, _P, _P]),
+    "adasap_residual_rows": (_I32, [_P, _P, _I64, _U64, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     "adasap_destroy": (None, [_P]),
     "adasap_sample_block": (_I32, [_U64, _U64, _U64, _I64, _I64, _P]),
     "adasap_normals": (_I32, [_U64, _U64, _U64, _I64, _P, _P]),
@@ -389,6 +390,17 @@ class Handle:
         a, m = ctypes.c_double(), ctypes.c_double()
         self.lib.check(self.lib.cdll.adasap_residual(self.h, _ptr(W), ctypes.byref(a), ctypes.byref(m)))
         return a.value, m.value
+
+    def residual_rows(self, W, m, seed, rows=False):
+        """Row-subsampled relative residual (estimate, worst column); with rows=True also the
+        sampled row indices (device int64 tensor)."""
+        torch = _torch()
+        _check_dev(W)
+        a, mx = ctypes.c_double(), ctypes.c_double()
+        R = torch.empty(m, dtype=torch.int64, device=W.device) if rows else None
+        self.lib.check(self.lib.cdll.adasap_residual_rows(self.h, _ptr(W), int(m), int(seed),
+                                                          ctypes.byref(a), ctypes.byref(mx), _ptr(R)))
+        return (a.value, mx.value, R) if rows else (a.value, mx.value)
 
     def block_gradient(self, t, Z):
         """(B_t, G) of Step I at iterate Z, through the solver's own Step-I launch."""

@@ -82,6 +82,7 @@ constexpr uint64_t PURPOSE_B = 5;
 constexpr uint64_t PURPOSE_OMEGA = 6;
 constexpr uint64_t PURPOSE_POW = 7;
 constexpr uint64_t PURPOSE_MINIBATCH = 11;  // warm-start training order, epoch = t
+constexpr uint64_t PURPOSE_RESROWS = 12;    // rows of a subsampled residual estimate
 constexpr uint64_t PURPOSE_SWEEP_STRIDE = 16;
 
 // ---- device-resident scalars of one iteration (never copied back inside the loop) -----------

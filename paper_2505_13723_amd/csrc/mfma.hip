@@ -349,10 +349,13 @@ struct MkArgs {
 // for the products with more than 64 right-hand sides.  Measured at the 2M-point, 64-column
 // shape: two row tiles at four waves per SIMD run 15% slower than four at two.
 constexpr int rt_of(int mode, int nq) { return (mode != MODE_F32V && nq > 4) ? 2 : 4; }
-// workgroups per CU the launch bounds ask for: two; the hi/lo products with more than 64
-// right-hand sides one, so that their accumulators fit in registers without spilling
+// workgroups per CU the launch bounds ask for: two; four for the float32 vector mode (k <= 4,
+// at most 128 VGPRs, more waves to hide the transcendental latency); the hi/lo products with
+// more than 64 right-hand sides one, so that their accumulators fit without spilling
 template <int MODE, int NQ>
-constexpr int mk_occupancy() { return (MODE == MODE_F16X3 && NQ > 4) ? 1 : 2; }
+constexpr int mk_occupancy() {
+  return MODE == MODE_F32V ? 4 : ((MODE == MODE_F16X3 && NQ > 4) ? 1 : 2);
+}
 
 // f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): indices stay
 // compile-time constants (a #pragma unroll loop over a register array can be left rolled,
@@ -730,7 +733,9 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
   const int rows_per_wg = WAVES * RT * 16;
   const int rwg = (int)((m + rows_per_wg - 1) / rows_per_wg);
   int splits;
-  if (wg_cap > 0) {
+  // a cap is honoured only if the capped grid still fills at least 4/5 of it (otherwise the
+  // product would lose more than the concurrent stream gains)
+  if (wg_cap > 0 && (wg_cap / rwg) * rwg * 5 >= wg_cap * 4) {
     // one resident round that leaves some workgroup slots free for a concurrent stream
     splits = wg_cap / rwg;
     if (splits > ntiles) splits = (int)(ntiles > 0 ? ntiles : 1);

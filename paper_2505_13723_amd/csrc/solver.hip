@@ -345,8 +345,13 @@ adasap_status_t residual_h(adasap_handle_t h, const void* W, DT wt, const void* 
   ep.lde2 = k;
   ep.a2 = -1.0;
   if (h->use_mfma) {
-    ADASAP_TRY(mfma_product(h->pack, nullptr, n, nullptr, 0, W, wt, k, mfma_mode_f16x3(), h->res.p,
-                            DT::F64, ep, h->mw, h->s));
+    // the residual runs alone: the full grid, not the Step-I cap
+    const int cap = h->mw.wg_cap;
+    h->mw.wg_cap = 0;
+    const adasap_status_t pst = mfma_product(h->pack, nullptr, n, nullptr, 0, W, wt, k,
+                                             mfma_mode_f16x3(), h->res.p, DT::F64, ep, h->mw, h->s);
+    h->mw.wg_cap = cap;
+    ADASAP_TRY(pst);
   } else {
     ADASAP_TRY(hk_kblock(h, n, n, h->X, nullptr, h->dtype, h->X, W, wt, k, k, h->res.p, DT::F64, k,
                          ep, ADASAP_FP64, h->s, h->part_kb));
@@ -718,6 +723,65 @@ adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres
   if (!h) return invalid("handle is null");
   if (!W) return invalid("W must be a non-null device pointer");
   return residual_h(h, W, h->dtype, h->Y, h->dtype, relres, relres_maxcol, false);
+}
+
+adasap_status_t adasap_residual_rows(adasap_handle_t h, const void* W, int64_t m, uint64_t seed,
+                                     double* relres, double* relres_maxcol, int64_t* rows_out) {
+  if (!h) return invalid("handle is null");
+  if (!W) return invalid("W must be a non-null device pointer");
+  if (m < 1 || m > h->n) return invalid("m must be in [1, n]");
+  const int64_t n = h->n;
+  const int k = h->k;
+  std::vector<int64_t> rows((size_t)m);
+  sample_block_host(seed, PURPOSE_RESROWS, 0, n, m, rows.data());
+  DevBuf rdev, yrows;
+  ADASAP_TRY(rdev.ensure((size_t)m * sizeof(int64_t)));
+  ADASAP_TRY(yrows.ensure((size_t)m * k * sizeof(double)));
+  ADASAP_TRY(h->res.ensure((size_t)m * k * sizeof(double)));
+  ADASAP_TRY(h->colq.ensure(2 * (size_t)k * sizeof(double)));
+  ADASAP_HIP(hipMemcpyAsync(rdev.p, rows.data(), (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
+  const int64_t* ridx = rdev.as<int64_t>();
+  KbEpilogue ep;
+  ep.E1 = W;
+  ep.e1t = h->dtype;
+  ep.e1idx = ridx;
+  ep.lde1 = k;
+  ep.a1 = h->cfg.lambda;
+  ep.E2 = h->Y;
+  ep.e2t = h->dtype;
+  ep.e2idx = ridx;
+  ep.lde2 = k;
+  ep.a2 = -1.0;
+  if (h->use_mfma) {
+    const int cap = h->mw.wg_cap;
+    h->mw.wg_cap = 0;
+    const adasap_status_t pst = mfma_product(h->pack, ridx, m, nullptr, 0, W, h->dtype, k,
+                                             mfma_mode_f16x3(), h->res.p, DT::F64, ep, h->mw, h->s);
+    h->mw.wg_cap = cap;
+    ADASAP_TRY(pst);
+  } else {
+    ADASAP_TRY(hk_kblock(h, m, n, h->X, ridx, h->dtype, h->X, W, h->dtype, k, k, h->res.p, DT::F64,
+                         k, ep, ADASAP_FP64, h->s, h->part_kb));
+  }
+  ADASAP_TRY(gather_rows(m, k, h->Y, h->dtype, k, ridx, yrows.p, DT::F64, k, h->s));
+  double* cq = h->colq.as<double>();
+  ADASAP_TRY(colsq(m, k, h->res.p, DT::F64, k, cq, h->tmp, h->s));
+  ADASAP_TRY(colsq(m, k, yrows.p, DT::F64, k, cq + k, h->tmp, h->s));
+  std::vector<double> hq(2 * (size_t)k);
+  ADASAP_HIP(hipMemcpyAsync(hq.data(), cq, 2 * (size_t)k * sizeof(double), hipMemcpyDeviceToHost, h->s));
+  if (rows_out)
+    ADASAP_HIP(hipMemcpyAsync(rows_out, ridx, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToDevice, h->s));
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  double rs = 0, ys = 0, mx = 0;
+  for (int c = 0; c < k; ++c) {
+    rs += hq[c];
+    ys += hq[k + c];
+    const double col = hq[k + c] > 0 ? std::sqrt(hq[c] / hq[k + c]) : std::sqrt(hq[c]);
+    mx = col > mx ? col : mx;
+  }
+  if (relres) *relres = ys > 0 ? std::sqrt(rs / ys) : std::sqrt(rs);
+  if (relres_maxcol) *relres_maxcol = mx;
+  return ADASAP_OK;
 }
 
 adasap_status_t adasap_block_gradient(adasap_handle_t h, int64_t t, const void* Z, int64_t* B_out,

@@ -177,3 +177,18 @@ def test_planted_transposed_kernel_block_is_caught(monkeypatch):
     X, Y, kind, ell, lam = _problem(n=200, d=3, k=1, lam=0.05)
     W, _ = A.adasap(X, Y, kind, ell, lam, b=50, r=20, iters=150, seed=5)
     assert linsys.relres(X, Y, W, kind, ell, lam)[0] > 1e-4
+
+
+def test_residual_rows_pins():
+    # at W = 0 the residual rows are exactly -Y[rows]; at the direct solution they vanish
+    from oracle import kernels as OK
+    from oracle import linsys as OL
+    from oracle import rng as OR
+    from paper_2505_13723_amd import inputs
+
+    X, Y = inputs.make_small(77, 400, 3, 2)
+    rows = OR.sample_block(5, 0, 400, 37, purpose=OR.PURPOSE_RESROWS)
+    assert np.array_equal(OL.residual_rows(X, Y, np.zeros_like(Y), OK.RBF, 0.7, 0.1, rows), -Y[rows])
+    Ws = OL.direct_solve(X, Y, OK.RBF, 0.7, 0.1)
+    r = OL.residual_rows(X, Y, Ws, OK.RBF, 0.7, 0.1, rows)
+    assert np.max(np.abs(r)) < 1e-9 * np.max(np.abs(Y))
