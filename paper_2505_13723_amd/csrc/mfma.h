@@ -27,7 +27,7 @@ struct MfmaPack {
 struct MfmaWork {
   DevBuf rhs, scale, tmp, part;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // when set, recorded around the product kernel
-  int wg_cap = 0;  // > 0: at most this many workgroups (leaves CU slots to a concurrent stream)
+  int cap_cus = 0;  // > 0: leave 1/8 of the workgroup slots of this many CUs to a concurrent stream
 };
 
 // A packed right-hand side (see mfma_pack_rhs_full).

@@ -727,15 +727,24 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
                        const int64_t* ridx, int64_t m, int d, int kern, const RhsDesc& rd, int k,
                        void* out, DT ot, const KbEpilogue& ep, DevBuf& part, hipStream_t s,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int ks_force = 0,
-                       int wg_cap = 0) {
+                       int cap_cus = 0) {
   if (m <= 0) return ADASAP_OK;
   const int RT = rt_of(rd.mode, rd.nq);
   const int rows_per_wg = WAVES * RT * 16;
   const int rwg = (int)((m + rows_per_wg - 1) / rows_per_wg);
   int splits;
-  // a cap is honoured only if the capped grid still fills at least 4/5 of it (otherwise the
-  // product would lose more than the concurrent stream gains)
-  if (wg_cap > 0 && (wg_cap / rwg) * rwg * 5 >= wg_cap * 4) {
+  // cap_cus > 0: one resident round of 7/4 workgroups per CU, for products of up to 64 row
+  // workgroups (longer products amortise the concurrent stream's work anyway), and only if
+  // the capped grid fills at least 9/10 of the cap.  Measured: a cap of 7/8 of the
+  // occupancy-4 slots of the float32 vector mode leaves the chain kernels no room (they need
+  // a CU with at most two product workgroups), so the cap counts two slots per CU.
+  int wg_cap = 0;
+  if (cap_cus > 0 && rwg <= 64) {
+    const int slots = cap_cus * 2;
+    wg_cap = slots - slots / 8;
+    if ((wg_cap / rwg) * rwg * 10 < wg_cap * 9) wg_cap = 0;
+  }
+  if (wg_cap > 0) {
     // one resident round that leaves some workgroup slots free for a concurrent stream
     splits = wg_cap / rwg;
     if (splits > ntiles) splits = (int)(ntiles > 0 ? ntiles : 1);
@@ -940,7 +949,7 @@ adasap_status_t mfma_product(const MfmaPack& pk, const int64_t* ridx, int64_t m,
   ADASAP_TRY(pack_rhs(R, rt, rows, k, k, nullptr, nt, mode, w.rhs, w.scale, w.tmp, rd, s));
   return mk_run(all_cols ? pk.cols.as<half8>() : static_cast<const half8*>(colsB), nt,
                 pk.rowv.as<half8>(), ridx, m, pk.d, pk.kern, rd, k, out, ot, ep, w.part, s, w.ev0,
-                w.ev1, 0, w.wg_cap);
+                w.ev1, 0, w.cap_cus);
 }
 
 adasap_status_t mfma_product_packed(const MfmaPack& pk, const int64_t* ridx, int64_t m,

@@ -346,11 +346,11 @@ adasap_status_t residual_h(adasap_handle_t h, const void* W, DT wt, const void* 
   ep.a2 = -1.0;
   if (h->use_mfma) {
     // the residual runs alone: the full grid, not the Step-I cap
-    const int cap = h->mw.wg_cap;
-    h->mw.wg_cap = 0;
+    const int cap = h->mw.cap_cus;
+    h->mw.cap_cus = 0;
     const adasap_status_t pst = mfma_product(h->pack, nullptr, n, nullptr, 0, W, wt, k,
                                              mfma_mode_f16x3(), h->res.p, DT::F64, ep, h->mw, h->s);
-    h->mw.wg_cap = cap;
+    h->mw.cap_cus = cap;
     ADASAP_TRY(pst);
   } else {
     ADASAP_TRY(hk_kblock(h, n, n, h->X, nullptr, h->dtype, h->X, W, wt, k, k, h->res.p, DT::F64, k,
@@ -578,12 +578,12 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   }
   if (hipMemsetAsync(h->scb.p, 0, sizeof(IterScalars), h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
   if (h->use_mfma) {
-    // the Step-I product runs as one resident round on 7/8 of the workgroup slots (two per
-    // CU), so that the second stream's sketch, Nystrom and powering kernels find room
+    // the Step-I product runs as one resident round on 7/8 of the workgroup slots, so that
+    // the second stream's sketch, Nystrom and powering kernels find room
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      h->mw.wg_cap = 2 * cus - cus / 4;
+      h->mw.cap_cus = cus;
     st = mfma_pack_create(h->pack, n, d, k, X, h->dtype, cfg->kernel, cfg->lengthscale, h->s);
     if (st == ADASAP_ERR_UNSUPPORTED && cfg->precision == ADASAP_FP32) {
       h->use_mfma = false;  // coordinates outside the float16 range: vector-ALU products
@@ -753,11 +753,11 @@ adasap_status_t adasap_residual_rows(adasap_handle_t h, const void* W, int64_t m
   ep.lde2 = k;
   ep.a2 = -1.0;
   if (h->use_mfma) {
-    const int cap = h->mw.wg_cap;
-    h->mw.wg_cap = 0;
+    const int cap = h->mw.cap_cus;
+    h->mw.cap_cus = 0;
     const adasap_status_t pst = mfma_product(h->pack, ridx, m, nullptr, 0, W, h->dtype, k,
                                              mfma_mode_f16x3(), h->res.p, DT::F64, ep, h->mw, h->s);
-    h->mw.wg_cap = cap;
+    h->mw.cap_cus = cap;
     ADASAP_TRY(pst);
   } else {
     ADASAP_TRY(hk_kblock(h, m, n, h->X, ridx, h->dtype, h->X, W, h->dtype, k, k, h->res.p, DT::F64,
