@@ -22,21 +22,23 @@ __device__ inline const void* adv(const void* p, DT t, int64_t e) {
 }
 
 // ---------------------------------------------------------------- Gram products P = A^T B
-constexpr int G_T = 16;      // output tile
-constexpr int G_ROWS = 32;   // rows staged per step
-constexpr int G_CHUNK = 1024;  // rows per split
+constexpr int G_T = 64;     // output tile of the Gram kernel (4 x 4 entries per thread)
+constexpr int G_ROWS = 16;  // rows staged per step
 
 // The small dense kernels of the Nystrom factors and of powering run on a second stream
 // beside the long kernel-block product; a raised wave priority lets their (few) waves win
 // instruction issue on the SIMDs they share with it.
 __device__ inline void raise_wave_priority() { __builtin_amdgcn_s_setprio(2); }
 
+// A^T B over a row range: a 64 x 64 output tile per workgroup, 4 x 4 entries per thread
+// (entries ty + 16 i, tx + 16 j, so the LDS reads of a wave are conflict-free), 16 rows
+// staged per barrier; blockIdx.z = problem * nsplit + row split.
 __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int p, int q,
                                                            const void* __restrict__ A, DT at,
                                                            int64_t lda, const void* __restrict__ B,
                                                            DT bt, int64_t ldb,
                                                            double* __restrict__ part, int nsplit,
-                                                           Batch bat) {
+                                                           int64_t chunk, Batch bat) {
   raise_wave_priority();
   __shared__ double As[G_ROWS][G_T];
   __shared__ double Bs[G_ROWS][G_T];
@@ -44,25 +46,48 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int p, 
   A = adv(A, at, prob * bat.sA);
   B = adv(B, bt, prob * bat.sB);
   part += (int64_t)prob * nsplit * p * q;
-  const int tx = threadIdx.x % G_T, ty = threadIdx.x / G_T;
-  const int pi = blockIdx.y * G_T + ty, qj = blockIdx.x * G_T + tx;
-  const int64_t r0 = (int64_t)split * G_CHUNK;
-  const int64_t r1 = r0 + G_CHUNK < rows ? r0 + G_CHUNK : rows;
-  double acc = 0.0;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int p0 = blockIdx.y * G_T, q0 = blockIdx.x * G_T;
+  const int64_t r0 = (int64_t)split * chunk;
+  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   for (int64_t rr = r0; rr < r1; rr += G_ROWS) {
-    for (int e = threadIdx.x; e < G_ROWS * G_T; e += 256) {
+#pragma unroll
+    for (int u = 0; u < (G_ROWS * G_T) / 256; ++u) {
+      const int e = threadIdx.x + u * 256;
       const int lr = e / G_T, lc = e % G_T;
       const int64_t row = rr + lr;
-      const int ca = blockIdx.y * G_T + lc, cb = blockIdx.x * G_T + lc;
-      As[lr][lc] = (row < r1 && ca < p) ? ld_any(A, at, row * lda + ca) : 0.0;
-      Bs[lr][lc] = (row < r1 && cb < q) ? ld_any(B, bt, row * ldb + cb) : 0.0;
+      As[lr][lc] = (row < r1 && p0 + lc < p) ? ld_any(A, at, row * lda + p0 + lc) : 0.0;
+      Bs[lr][lc] = (row < r1 && q0 + lc < q) ? ld_any(B, bt, row * ldb + q0 + lc) : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int l = 0; l < G_ROWS; ++l) acc += As[l][ty] * Bs[l][tx];
+#pragma unroll
+    for (int l = 0; l < G_ROWS; ++l) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[l][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[l][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
     __syncthreads();
   }
-  if (pi < p && qj < q) part[((int64_t)split * p + pi) * q + qj] = acc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int pi = p0 + ty + 16 * i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int qj = q0 + tx + 16 * j;
+      if (pi < p && qj < q) part[((int64_t)split * p + pi) * q + qj] = acc[i][j];
+    }
+  }
 }
 
 __global__ void gram_reduce_kernel(const double* __restrict__ part, int splits, int p, int q,
@@ -741,12 +766,20 @@ adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t l
     ADASAP_LAUNCH_CHECK();
     return ADASAP_OK;
   }
-  int splits = (int)((rows + G_CHUNK - 1) / G_CHUNK);
-  if (splits < 1) splits = 1;
+  // row splits: about 256 workgroups per launch, at least 64 rows each
+  const int tiles = ((q + G_T - 1) / G_T) * ((p + G_T - 1) / G_T);
+  int64_t want = (256 + (int64_t)tiles * NP - 1) / ((int64_t)tiles * NP);
+  const int64_t most = (rows + 63) / 64;
+  if (want > most) want = most;
+  if (want < 1) want = 1;
+  int64_t chunk = (rows + want - 1) / want;
+  chunk = (chunk + G_ROWS - 1) / G_ROWS * G_ROWS;
+  if (chunk < G_ROWS) chunk = G_ROWS;
+  const int splits = (int)((rows + chunk - 1) / chunk > 0 ? (rows + chunk - 1) / chunk : 1);
   ADASAP_TRY(part.ensure((size_t)NP * splits * p * q * sizeof(double)));
   const dim3 grid((q + G_T - 1) / G_T, (p + G_T - 1) / G_T, splits * NP);
   hipLaunchKernelGGL(gram_partial_kernel, grid, dim3(256), 0, s, rows, p, q, A, at, lda, B, bt,
-                     ldb, part.as<double>(), splits, bat);
+                     ldb, part.as<double>(), splits, chunk, bat);
   ADASAP_LAUNCH_CHECK();
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((p * q + 255) / 256, NP), dim3(256), 0, s,
                      part.as<double>(), splits, p, q, rowscale, P, bat);

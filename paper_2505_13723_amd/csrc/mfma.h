@@ -28,6 +28,7 @@ struct MfmaWork {
   DevBuf rhs, scale, tmp, part;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // when set, recorded around the product kernel
   int cap_cus = 0;  // > 0: leave 1/8 of the workgroup slots of this many CUs to a concurrent stream
+  hipEvent_t wait_ev = nullptr;  // when set, the product kernel (not the packing) waits for it
 };
 
 // A packed right-hand side (see mfma_pack_rhs_full).

@@ -259,15 +259,30 @@ __global__ void rhspack16_kernel(const void* __restrict__ R, DT rt, int64_t rows
   out += (int64_t)blockIdx.y * ntiles * NQ * parts * 64;
   half8 hi, lo;
   const float inv = rhs < k ? 1.0f / scale[rhs] : 0.0f;
+  // branch-free gathers (invalid slots read element 0 and are zeroed), so that the eight
+  // loads of a thread are in flight together
+  int64_t off[8];
+  bool ok[8];
+#pragma unroll
   for (int m = 0; m < 8; ++m) {
     const int64_t col = T * TILE + slot_col(lane, m);
-    float v = 0.0f;
-    if (col < rows && rhs < k) {
-      const int64_t src = idx ? idx[col] : col;
-      const double x = rt == DT::F64 ? static_cast<const double*>(R)[src * ldr + rhs]
-                                     : (double)static_cast<const float*>(R)[src * ldr + rhs];
-      v = (float)(x * (double)inv);
-    }
+    ok[m] = col < rows && rhs < k;
+    const int64_t src = idx ? idx[ok[m] ? col : 0] : col;
+    off[m] = ok[m] ? src * ldr + rhs : 0;
+  }
+  double x[8];
+  if (rt == DT::F64) {
+    const double* Rd = static_cast<const double*>(R);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[m] = Rd[off[m]];
+  } else {
+    const float* Rf = static_cast<const float*>(R);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[m] = (double)Rf[off[m]];
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const float v = ok[m] ? (float)(x[m] * (double)inv) : 0.0f;
     const _Float16 h = (_Float16)v;
     hi[m] = h;
     lo[m] = (_Float16)(v - (float)h);
@@ -328,7 +343,7 @@ struct MkArgs {
   int64_t tiles_per_split;
   int splits;
   int rwg;               // row workgroups
-  int xcd_map;           // 1: splits grouped by XCD
+  int xcd_map;           // 1: split-major items grouped by XCD (grid a multiple of 8)
   float* part;           // [splits][m][k]
   int k;
   float p;               // Matern factor
@@ -563,11 +578,13 @@ __global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkA
   const int prob = blockIdx.y;
   int split, rw;
   if (a.xcd_map) {
-    // workgroups are dealt round-robin to the 8 XCDs: keep every row workgroup of one column
-    // split on the same XCD so they share the split's column stream in that XCD's L2
-    const int xcd = bid % 8, local = bid / 8;
-    split = xcd + 8 * (local / a.rwg);
-    rw = local % a.rwg;
+    // workgroups are dealt round-robin to the 8 XCDs: XCD x runs items
+    // [x * grid/8, (x+1) * grid/8) of the split-major order, so the row workgroups of one
+    // column split sit on one or two XCDs and share the split's column stream in their L2
+    const int per = (int)gridDim.x / 8;
+    const int item = (bid % 8) * per + bid / 8;
+    split = item / a.rwg;
+    rw = item % a.rwg;
   } else {
     split = bid / a.rwg;
     rw = bid % a.rwg;
@@ -759,7 +776,7 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
   if (tps < 1) tps = 1;
   splits = (int)((ntiles + tps - 1) / tps);
   if (splits < 1) splits = 1;
-  const int xcd_map = (splits % 8 == 0) ? 1 : 0;
+  const int xcd_map = ((int64_t)rwg * splits % 8 == 0) ? 1 : 0;
   ADASAP_TRY(part.ensure((size_t)splits * m * k * sizeof(float)));
   MkArgs a{};
   a.colA = colA;
@@ -947,6 +964,7 @@ adasap_status_t mfma_product(const MfmaPack& pk, const int64_t* ridx, int64_t m,
   const int64_t rows = all_cols ? pk.n : ncols;
   RhsDesc rd;
   ADASAP_TRY(pack_rhs(R, rt, rows, k, k, nullptr, nt, mode, w.rhs, w.scale, w.tmp, rd, s));
+  if (w.wait_ev) ADASAP_HIP(hipStreamWaitEvent(s, w.wait_ev, 0));
   return mk_run(all_cols ? pk.cols.as<half8>() : static_cast<const half8*>(colsB), nt,
                 pk.rowv.as<half8>(), ridx, m, pk.d, pk.kern, rd, k, out, ot, ep, w.part, s, w.ev0,
                 w.ev1, 0, w.cap_cus);

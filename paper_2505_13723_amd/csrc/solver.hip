@@ -71,6 +71,7 @@ struct adasap_handle_s {
   DevBuf part_kb2, part_g2, coef2;  // second-stream scratch
   hipStream_t s2 = nullptr;         // second stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_sketch = nullptr;   // the sketch of the current block is complete
   DevBuf colsB;   // column fragments of the current block
   DevBuf rowq;    // row vectors of prediction points
   int64_t* Bhost[2] = {nullptr, nullptr};
@@ -88,6 +89,7 @@ struct adasap_handle_s {
     for (hipEvent_t e : kev) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_sketch) (void)hipEventDestroy(ev_sketch);
     if (s2) (void)hipStreamDestroy(s2);
     for (int i = 0; i < 2; ++i) {
       if (Bhost[i]) (void)hipHostFree(Bhost[i]);
@@ -195,16 +197,41 @@ adasap_status_t block_gradient_h(adasap_handle_t h, const int64_t* B, const void
                    h->part_kb);
 }
 
+// The head of the second stream's chain for block B: its column fragments (or gathered
+// rows), Omega_t and the sketch K_{BB} Omega_t (Step II); ev_sketch marks the sketch.
+adasap_status_t iter_head(adasap_handle_t h, const int64_t* B, int64_t t, uint64_t off) {
+  const adasap_config_t& c = h->cfg;
+  const int64_t b = c.block_size;
+  const int r = c.rank, d = h->d;
+  const int kprec = c.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
+  hipStream_t s2 = h->s2;
+  if (h->use_mfma) ADASAP_TRY(mfma_pack_block(h->pack, B, b, h->colsB, s2));
+  else ADASAP_TRY(gather_rows(b, d, h->X, h->dtype, d, B, h->XB.p, h->dtype, d, s2));
+  if (c.precond == ADASAP_PRECOND_NYSTROM) {
+    ADASAP_TRY(normals_dev(c.seed, PURPOSE_OMEGA + off, (uint64_t)t, b * r, h->Om.as<double>(), s2));
+    KbEpilogue none;
+    if (h->use_mfma)
+      ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, h->Om.p, DT::F64, r, mfma_mode_f16x3(),
+                              h->Ysk.p, DT::F64, none, h->mw2, s2));
+    else
+      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, h->Om.p, DT::F64, r, r,
+                           h->Ysk.p, DT::F64, r, none, kprec, s2, h->part_kb2));
+    ADASAP_HIP(hipEventRecord(h->ev_sketch, s2));
+  }
+  return ADASAP_OK;
+}
+
 // one ADASAP iteration; rhs is the current right-hand side (Y or a refinement residual)
 adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* rhs, DT rhst,
                         void* Wout) {
   const adasap_config_t& c = h->cfg;
   const int64_t n = h->n, b = c.block_size;
-  const int k = h->k, r = c.rank, d = h->d;
+  const int k = h->k, r = c.rank;
   hipStream_t s = h->s;
   IterScalars* sc = h->scb.as<IterScalars>();
   const int prec = c.precision;
   const int kprec = prec == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
+  const bool nys = c.precond == ADASAP_PRECOND_NYSTROM;
 
   // Step I: block B_t (host Floyd -> pinned slot -> device)
   const int slot = (int)(t & 1);
@@ -213,12 +240,16 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   ADASAP_HIP(hipMemcpyAsync(h->Bdev.p, h->Bhost[slot], b * sizeof(int64_t), hipMemcpyHostToDevice, s));
   ADASAP_HIP(hipEventRecord(h->bev[slot], s));
   const int64_t* B = h->Bdev.as<int64_t>();
-  if (!h->use_mfma) ADASAP_TRY(gather_rows(b, d, h->X, h->dtype, d, B, h->XB.p, h->dtype, d, s));
-  // the sketch, the Nystrom factors and the step size do not depend on the block gradient:
-  // they run on a second stream while the main stream evaluates K_{B,:} Z
+  // The sketch, the Nystrom factors and the step size do not depend on the block gradient:
+  // they run on a second stream while the main stream evaluates K_{B,:} Z.  At MIXED
+  // precision that chain of mostly small kernels is the longer of the two, so its head, the
+  // sketch, runs with the whole GPU (the main stream packs Z meanwhile) and the Step-I
+  // product waits for it; at the other precisions the two start together.
   hipStream_t s2 = h->s2;
   ADASAP_HIP(hipEventRecord(h->ev_fork, s));
   ADASAP_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
+  ADASAP_TRY(iter_head(h, B, t, off));
+  const bool sketch_first = nys && h->use_mfma && prec == ADASAP_MIXED;
 
   // gradient block at Z (accelerated; the reading of Alg. 2 Step IV), at W_t (accelerated,
   // printed form) or at the iterate (plain steps keep the iterate in Z)
@@ -243,26 +274,17 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
     }
     h->mw.ev0 = h->kev[2 * slot];
     h->mw.ev1 = h->kev[2 * slot + 1];
+    h->mw.wait_ev = sketch_first ? h->ev_sketch : nullptr;
     ++h->kev_used;
     const adasap_status_t pst = block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s);
     h->mw.ev0 = h->mw.ev1 = nullptr;
+    h->mw.wait_ev = nullptr;
     ADASAP_TRY(pst);
-    ADASAP_TRY(mfma_pack_block(h->pack, B, b, h->colsB, s2));
   } else {
     ADASAP_TRY(block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s));
   }
 
-  const bool nys = c.precond == ADASAP_PRECOND_NYSTROM;
   if (nys) {
-    // Step II: sketch
-    ADASAP_TRY(normals_dev(c.seed, PURPOSE_OMEGA + off, (uint64_t)t, b * r, h->Om.as<double>(), s2));
-    KbEpilogue none;
-    if (h->use_mfma)
-      ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, h->Om.p, DT::F64, r, mfma_mode_f16x3(),
-                              h->Ysk.p, DT::F64, none, h->mw2, s2));
-    else
-      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, h->Om.p, DT::F64, r, r,
-                           h->Ysk.p, DT::F64, r, none, kprec, s2, h->part_kb2));
     // Step III: Nystrom factors
     ADASAP_TRY(gram(b, r, r, h->Om.p, DT::F64, r, h->Ysk.p, DT::F64, r, h->Mo.as<double>(), nullptr,
                     h->part_g2, s2));
@@ -572,6 +594,7 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
       hipEventCreateWithFlags(&h->bev[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_sketch, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking) != hipSuccess) {
     set_error("event creation failed");
     return fail(ADASAP_ERR_DEVICE);
