@@ -365,11 +365,12 @@ struct MkArgs {
 // shape: two row tiles at four waves per SIMD run 15% slower than four at two.
 constexpr int rt_of(int mode, int nq) { return (mode != MODE_F32V && nq > 4) ? 2 : 4; }
 // workgroups per CU the launch bounds ask for: two; four for the float32 vector mode (k <= 4,
-// at most 128 VGPRs, more waves to hide the transcendental latency); the hi/lo products with
-// more than 64 right-hand sides one, so that their accumulators fit without spilling
-template <int MODE, int NQ>
+// at most 128 VGPRs, more waves to hide the transcendental latency); one for the hi/lo
+// products with eight column tiles of the Matern-3/2 and -5/2 kernels, whose registers do
+// not fit two waves per SIMD without scratch
+template <int KERN, int MODE, int NQ>
 constexpr int mk_occupancy() {
-  return MODE == MODE_F32V ? 4 : ((MODE == MODE_F16X3 && NQ > 4) ? 1 : 2);
+  return MODE == MODE_F32V ? 4 : ((MODE == MODE_F16X3 && NQ > 7 && KERN >= 2) ? 1 : 2);
 }
 
 // f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): indices stay
@@ -435,8 +436,18 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
   // barrier per tile: while the waves compute tile T from one LDS buffer, tile T+1 is written
   // to the other and tile T+2 is in flight in registers
   constexpr int LOADS16 = (A_FR + R_FR + (R_F32 * 4) / 16 + 255) / 256;
+  // separate members rather than an array: an array of five 16-byte words is kept in scratch
+  static_assert(LOADS16 <= 5, "tile loads per thread");
   struct Stage {
-    uint4 v[LOADS16];
+    uint4 w0, w1, w2, w3, w4;
+  };
+  auto word = [](Stage& st, auto uc) __attribute__((always_inline)) -> uint4& {
+    constexpr int u = decltype(uc)::value;
+    if constexpr (u == 0) return st.w0;
+    else if constexpr (u == 1) return st.w1;
+    else if constexpr (u == 2) return st.w2;
+    else if constexpr (u == 3) return st.w3;
+    else return st.w4;
   };
   // branch-free loads (one basic block, so the wait before each LDS store covers exactly the
   // older of the two register stages); lanes past the tile's data read a valid dummy address.
@@ -449,15 +460,15 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
       constexpr int u = decltype(uc)::value;
       const int e = tid + u * 256;
       const uint4* src = e < A_FR ? ca + e : (e < TOTAL16 ? rb + (e - A_FR) : ca);
-      st.v[u] = *src;
+      word(st, uc) = *src;
     });
     return st;
   };
-  auto sstore = [&](const Stage& st, int buf) __attribute__((always_inline)) {
+  auto sstore = [&](Stage st, int buf) __attribute__((always_inline)) {
     uint4* dst = reinterpret_cast<uint4*>(lds + buf * BUF_BYTES);
     static_for<LOADS16>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
-      dst[tid + u * 256] = st.v[u];
+      dst[tid + u * 256] = word(st, uc);
     });
   };
   auto compute = [&](int buf) __attribute__((always_inline)) {
@@ -572,7 +583,7 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
 }
 
 template <int KS, int KERN, int MODE, int NQ, int RT>
-__global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkArgs a) {
+__global__ __launch_bounds__(256, (mk_occupancy<KERN, MODE, NQ>())) void mk_kernel(MkArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[2 * MkShape<KS, MODE, NQ>::BUF_BYTES];
   const int bid = blockIdx.x;
   const int prob = blockIdx.y;
@@ -602,7 +613,7 @@ __global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mk_kernel(MkA
 // workgroup takes (problem, row workgroup, tile range) items from a global counter until the
 // table is exhausted; item i writes its partial sums to part[i][rows of its workgroup][k].
 template <int KS, int KERN, int MODE, int NQ, int RT>
-__global__ __launch_bounds__(256, (mk_occupancy<MODE, NQ>())) void mkq_kernel(MkArgs a) {
+__global__ __launch_bounds__(256, (mk_occupancy<KERN, MODE, NQ>())) void mkq_kernel(MkArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[2 * MkShape<KS, MODE, NQ>::BUF_BYTES];
   __shared__ int s_item;
   constexpr int ROWS = WAVES * RT * 16;
