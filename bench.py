@@ -54,10 +54,11 @@ METRIC = "time to rel. residual 1e-3 (s) & kernel-block GFLOP/s, n=2M d=11, 1 GP
 PEAK_F16_MFMA_TFLOPS = 2500.0
 # transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 8 lanes per clock x 2.4 GHz
 PEAK_EXP_TPS = 256 * 4 * 8 * 2.4e9 / 1e12
-# HBM bytes of one Step-I launch at the 2M-point, 64-column shape: rocprofv3 FETCH_SIZE +
-# WRITE_SIZE of the launch (2.009e6 + 2.867e4 KiB), each scaled by 1.0486, the ratio of true to
-# counted bytes for a 1 GiB copy (profiles/mk_kernel_rbf_n2m_d11_k64.md)
-STEP1_TRAFFIC_BYTES_N2M = 2.19e9
+# HBM bytes of one Step-I launch at the 2M-point, 64-column shape: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE of the launch (9.16e5 and 2.867e4 KiB), each scaled by the ratio of true to
+# counted KiB of a 1 GiB copy in the same run (2.0 for FETCH_SIZE, which prices the 128-byte
+# reads of gfx950 at 64 bytes, and 1.0 for WRITE_SIZE); profiles/mk_kernel_rbf_n2m_d11_k64.md
+STEP1_TRAFFIC_BYTES_N2M = 1.905e9
 
 
 def log(msg):

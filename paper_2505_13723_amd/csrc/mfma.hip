@@ -471,8 +471,46 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
       dst[tid + u * 256] = word(st, uc);
     });
   };
+  // float16 mode, software-pipelined over tiles: the K Z products of a tile run in the
+  // compute step of the next one, from the K and right-hand-side fragments kept in registers,
+  // so that they overlap the next tile's distances and exponentials instead of waiting for
+  // this tile's.  Each accumulator still adds the tiles in order.  Zero fragments before the
+  // first tile make the first (and, with no tiles, the only) deferred step add nothing.
+  constexpr bool PIPE = MODE == MODE_F16;
+  half8 Kp[PIPE ? RT : 1];
+  half8 Rp[PIPE ? NQ : 1];
+  static_for<PIPE ? RT : 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Kp[i][j] = (_Float16)0.0f;
+  });
+  static_for<PIPE ? NQ : 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Rp[i][j] = (_Float16)0.0f;
+  });
+  auto kz_deferred = [&]() __attribute__((always_inline)) {
+    if constexpr (PIPE) {
+      static_for<RT>([&](auto rc) {
+        constexpr int rt = decltype(rc)::value;
+        static_for<NQ>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          acc[rt][q] = mfma16(Rp[q], Kp[rt], acc[rt][q]);
+        });
+      });
+    }
+  };
+
   auto compute = [&](int buf) __attribute__((always_inline)) {
     const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
+    if constexpr (PIPE) {
+      kz_deferred();
+      const half8* Rf = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES + A_FR * 16);
+      static_for<NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        Rp[q] = Rf[q * 64 + lane];
+      });
+    }
     half8 A[2][KS];
 #pragma unroll
     for (int cs = 0; cs < 2; ++cs)
@@ -508,8 +546,8 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
         for (int j = 0; j < 8; ++j) Kh[j] = (_Float16)kv[j];
         const half8* Rf = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES + A_FR * 16);
         if constexpr (MODE == MODE_F16) {
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) acc[rt][q] = mfma16(Rf[q * 64 + lane], Kh, acc[rt][q]);
+          (void)Rf;
+          Kp[rt] = Kh;
         } else {
           half8 Kl;
 #pragma unroll
@@ -552,6 +590,7 @@ __device__ void mk_tiles(const MkArgs& a, char* lds, const half8* colA_p, const 
     }
     if (T < T1) compute(0);  // odd count: the last tile is in buffer 0
   }
+  kz_deferred();  // the last tile's K Z products
 
   // write partial sums
   if constexpr (MODE == MODE_F32V) {
