@@ -55,10 +55,10 @@ PEAK_F16_MFMA_TFLOPS = 2500.0
 # transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 8 lanes per clock x 2.4 GHz
 PEAK_EXP_TPS = 256 * 4 * 8 * 2.4e9 / 1e12
 # HBM bytes of one Step-I launch at the 2M-point, 64-column shape: rocprofv3 FETCH_SIZE and
-# WRITE_SIZE of the launch (9.16e5 and 2.867e4 KiB), each scaled by the ratio of true to
+# WRITE_SIZE of the launch (7.637e5 and 2.867e4 KiB), each scaled by the ratio of true to
 # counted KiB of a 1 GiB copy in the same run (2.0 for FETCH_SIZE, which prices the 128-byte
 # reads of gfx950 at 64 bytes, and 1.0 for WRITE_SIZE); profiles/mk_kernel_rbf_n2m_d11_k64.md
-STEP1_TRAFFIC_BYTES_N2M = 1.905e9
+STEP1_TRAFFIC_BYTES_N2M = 1.593e9
 
 
 def log(msg):
