@@ -800,14 +800,15 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
   const int rows_per_wg = WAVES * RT * 16;
   const int rwg = (int)((m + rows_per_wg - 1) / rows_per_wg);
   int splits;
-  // cap_cus > 0: one resident round of 7/4 workgroups per CU, for products of up to 64 row
-  // workgroups (longer products amortise the concurrent stream's work anyway), and only if
-  // the capped grid fills at least 9/10 of the cap.  Measured: a cap of 7/8 of the
-  // occupancy-4 slots of the float32 vector mode leaves the chain kernels no room (they need
-  // a CU with at most two product workgroups), so the cap counts two slots per CU.
+  // cap_cus > 0: one resident round on 7/8 of two workgroup slots per CU (three for the
+  // float32 vector mode, whose 128-VGPR workgroups leave a SIMD 128 registers beside three of
+  // them), for products of up to 64 row workgroups (longer products amortise the concurrent
+  // stream's work anyway), and only if the capped grid fills at least 9/10 of the cap.
+  // Measured at the vector mode: 7/8 of four slots per CU, or all of three, leaves the second
+  // stream's kernels too little room and the iteration is slower.
   int wg_cap = 0;
   if (cap_cus > 0 && rwg <= 64) {
-    const int slots = cap_cus * 2;
+    const int slots = cap_cus * (rd.mode == MODE_F32V ? 3 : 2);
     wg_cap = slots - slots / 8;
     if ((wg_cap / rwg) * rwg * 10 < wg_cap * 9) wg_cap = 0;
   }

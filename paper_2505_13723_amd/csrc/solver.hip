@@ -241,15 +241,15 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   ADASAP_HIP(hipEventRecord(h->bev[slot], s));
   const int64_t* B = h->Bdev.as<int64_t>();
   // The sketch, the Nystrom factors and the step size do not depend on the block gradient:
-  // they run on a second stream while the main stream evaluates K_{B,:} Z.  At MIXED
-  // precision that chain of mostly small kernels is the longer of the two, so its head, the
-  // sketch, runs with the whole GPU (the main stream packs Z meanwhile) and the Step-I
-  // product waits for it; at the other precisions the two start together.
+  // they run on a second stream while the main stream evaluates K_{B,:} Z.  The head of that
+  // chain, the sketch, is a matrix-core product that would compete with Step I, so it runs
+  // first with the whole GPU (the main stream packs Z meanwhile) and the Step-I product
+  // waits for it; the rest of the chain, mostly small kernels, runs beside Step I.
   hipStream_t s2 = h->s2;
   ADASAP_HIP(hipEventRecord(h->ev_fork, s));
   ADASAP_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
   ADASAP_TRY(iter_head(h, B, t, off));
-  const bool sketch_first = nys && h->use_mfma && prec == ADASAP_MIXED;
+  const bool sketch_first = nys && h->use_mfma;
 
   // gradient block at Z (accelerated; the reading of Alg. 2 Step IV), at W_t (accelerated,
   // printed form) or at the iterate (plain steps keep the iterate in Z)
