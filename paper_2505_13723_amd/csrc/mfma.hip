@@ -33,14 +33,29 @@ namespace {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int TILE = 32;      // columns per tile
 constexpr int WAVES = 4;      // waves per workgroup
 constexpr int MODE_F16 = 0, MODE_F16X3 = 1, MODE_F32V = 2;
+// MODE_F16 on 32x32x16 MFMAs ("wide" tiles), for 17 to 64 right-hand sides
+constexpr int MODE_F16W = 3;
 constexpr int ROWVEC = 64;    // float16 entries stored per point (two K-steps)
 
 __device__ inline f4 mfma16(half8 a, half8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f16v mfma32(half8 a, half8 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// Wide tiles: column (within the tile) of index kappa of K-slice t.  The 32x32x16 MFMA leaves
+// lane l of a 32 x 32 (column x row) distance block with row l % 32 and, in register r, column
+// 8 (r / 4) + 4 (l / 32) + r % 4; registers 8t..8t+7 are the B operand of K-slice t of the
+// K Z product (index kappa = 8 (l / 32) + j), so the right-hand side is packed in this order.
+__host__ __device__ constexpr int wide_col(int t, int kappa) {
+  return 16 * t + 8 * ((kappa % 8) / 4) + 4 * (kappa / 8) + kappa % 4;
 }
 
 // ---------------------------------------------------------------- packing
@@ -290,6 +305,44 @@ __global__ void rhspack16_kernel(const void* __restrict__ R, DT rt, int64_t rows
   const int64_t base = (T * NQ + q) * parts;
   out[(base + 0) * 64 + lane] = hi;
   if (parts == 2) out[(base + 1) * 64 + lane] = lo;
+}
+
+// float16 right-hand side for wide tiles: per tile, NQW blocks of 32 right-hand sides and two
+// K-slices of 16 columns, lane l holding right-hand side 32q + l % 32 and the eight columns
+// wide_col(t, 8 (l / 32) + j), scaled as rhspack16_kernel does
+__global__ void rhspackw_kernel(const void* __restrict__ R, DT rt, int64_t rows, int k,
+                                int64_t ldr, const float* __restrict__ scale, int64_t ntiles,
+                                int NQW, half8* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ntiles * NQW * 128) return;
+  const int lane = (int)(e % 64);
+  const int t = (int)((e / 64) % 2);
+  const int q = (int)((e / 128) % NQW);
+  const int64_t T = e / (128 * (int64_t)NQW);
+  const int rhs = q * 32 + lane % 32;
+  const float inv = rhs < k ? 1.0f / scale[rhs] : 0.0f;
+  int64_t off[8];
+  bool ok[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t col = T * TILE + wide_col(t, 8 * (lane / 32) + j);
+    ok[j] = col < rows && rhs < k;
+    off[j] = ok[j] ? col * ldr + rhs : 0;
+  }
+  double x[8];
+  if (rt == DT::F64) {
+    const double* Rd = static_cast<const double*>(R);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = Rd[off[j]];
+  } else {
+    const float* Rf = static_cast<const float*>(R);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = (double)Rf[off[j]];
+  }
+  half8 h;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h[j] = (_Float16)(ok[j] ? (float)(x[j] * (double)inv) : 0.0f);
+  out[((T * NQW + q) * 2 + t) * 64 + lane] = h;
 }
 
 // float32 right-hand side, padded to ntiles*32 rows and KC columns
@@ -648,6 +701,219 @@ __global__ __launch_bounds__(256, (mk_occupancy<KERN, MODE, NQ>())) void mk_kern
       a.part + prob * a.bs_part + (int64_t)split * a.m * a.k, 0);
 }
 
+// Wide tiles (MODE_F16W): the float16 mode on 32x32x16 MFMAs.  A wave takes two row tiles of
+// 32 (64 rows, as the 16x16 form) against each column tile of 32.  The distance takes NS
+// K-slices of 16 slots (NS = 3 for 3d + 6 <= 48, against 64 slots on 16x16x32), with the
+// column fragments read from the same LDS tile in the 32x32 operand order (A[m][k] in lane
+// m + 32 (k / 8), element k % 8) and the row fragments from the row vectors.  The K Z products
+// are software-pipelined by one tile as in the 16x16 form; each accumulator adds the tiles
+// in order.
+template <int KS, int NS, int KERN, int NQW>
+__device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const void* rhs_p,
+                          const int64_t* ridx, int rw, int64_t T0, int64_t T1, float* out) {
+  constexpr int A_FR = 2 * KS * 64, R_FR = NQW * 2 * 64, TOTAL16 = A_FR + R_FR;
+  constexpr int BUF_BYTES = ((TOTAL16 + 255) / 256) * 256 * 16;
+  constexpr int LOADS16 = (TOTAL16 + 255) / 256;
+  static_assert(NS >= 1 && NS <= 2 * KS, "K-slices within the packed slots");
+  static_assert(LOADS16 <= 5, "tile loads per thread");
+  const int tid = threadIdx.x;
+  const int lane = tid % 64;
+  const int wave = tid / 64;
+  const int g = lane / 32;
+  const int64_t row_base = ((int64_t)rw * WAVES + wave) * 64;
+  // row fragments (B operand: B[k][n] in lane n + 32 (k / 8), element k % 8)
+  half8 Bfr[2][NS];
+  static_for<2>([&](auto rc) {
+    constexpr int rt = decltype(rc)::value;
+    const int64_t row = row_base + rt * 32 + lane % 32;
+    const int64_t pt = row < a.m ? (ridx ? ridx[row] : row) : (ridx ? ridx[0] : 0);
+    static_for<NS>([&](auto sc) {
+      constexpr int sl = decltype(sc)::value;
+      Bfr[rt][sl] = a.rowv[pt * 8 + 2 * sl + g];
+    });
+  });
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) asm volatile("" ::"v"(Bfr[rt][sl]));
+  // LDS positions of this lane's column fragments: column c = lane % 32, slots 16 s + 8 g..,
+  // stored as [column half][K-step of 32][slot group of 8][16 columns]
+  int aidx[NS];
+  {
+    const int c = lane % 32;
+    static_for<NS>([&](auto sc) {
+      constexpr int sl = decltype(sc)::value;
+      const int hb = 2 * sl + g;
+      aidx[sl] = ((c / 16) * KS + hb / 4) * 64 + (hb % 4) * 16 + c % 16;
+    });
+  }
+  f16v acc[2][NQW];
+  half8 Kp[2][2];
+  half8 Rp[NQW][2];
+  static_for<2>([&](auto rc) {
+    constexpr int rt = decltype(rc)::value;
+    static_for<NQW>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[rt][q][r] = 0.0f;
+    });
+  });
+  static_for<2>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      Kp[i][0][j] = (_Float16)0.0f;
+      Kp[i][1][j] = (_Float16)0.0f;
+    }
+  });
+  static_for<NQW>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      Rp[q][0][j] = (_Float16)0.0f;
+      Rp[q][1][j] = (_Float16)0.0f;
+    }
+  });
+
+  struct Stage {
+    uint4 w0, w1, w2, w3, w4;
+  };
+  auto word = [](Stage& st, auto uc) __attribute__((always_inline)) -> uint4& {
+    constexpr int u = decltype(uc)::value;
+    if constexpr (u == 0) return st.w0;
+    else if constexpr (u == 1) return st.w1;
+    else if constexpr (u == 2) return st.w2;
+    else if constexpr (u == 3) return st.w3;
+    else return st.w4;
+  };
+  auto gload = [&](int64_t T) __attribute__((always_inline)) -> Stage {
+    Stage st;
+    const uint4* ca = reinterpret_cast<const uint4*>(colA_p) + T * A_FR;
+    const uint4* rb = reinterpret_cast<const uint4*>(rhs_p) + T * R_FR;
+    static_for<LOADS16>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const int e = tid + u * 256;
+      const uint4* src = e < A_FR ? ca + e : (e < TOTAL16 ? rb + (e - A_FR) : ca);
+      word(st, uc) = *src;
+    });
+    return st;
+  };
+  auto sstore = [&](Stage st, int buf) __attribute__((always_inline)) {
+    uint4* dst = reinterpret_cast<uint4*>(lds + buf * BUF_BYTES);
+    static_for<LOADS16>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      dst[tid + u * 256] = word(st, uc);
+    });
+  };
+  auto kz_deferred = [&]() __attribute__((always_inline)) {
+    static_for<2>([&](auto rc) {
+      constexpr int rt = decltype(rc)::value;
+      static_for<NQW>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        acc[rt][q] = mfma32(Rp[q][0], Kp[rt][0], acc[rt][q]);
+        acc[rt][q] = mfma32(Rp[q][1], Kp[rt][1], acc[rt][q]);
+      });
+    });
+  };
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
+    kz_deferred();
+    const half8* Rf = Af + A_FR;
+    static_for<NQW>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      Rp[q][0] = Rf[(q * 2 + 0) * 64 + lane];
+      Rp[q][1] = Rf[(q * 2 + 1) * 64 + lane];
+    });
+    half8 A[NS];
+    static_for<NS>([&](auto sc) {
+      constexpr int sl = decltype(sc)::value;
+      A[sl] = Af[aidx[sl]];
+    });
+    static_for<2>([&](auto rc) {
+      constexpr int rt = decltype(rc)::value;
+      f16v D;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) D[r] = 0.0f;
+      static_for<NS>([&](auto sc) {
+        constexpr int sl = decltype(sc)::value;
+        D = mfma32(A[sl], Bfr[rt][sl], D);
+      });
+      static_for<2>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        half8 Kh;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Kh[j] = (_Float16)kval<KERN>(D[8 * t + j], a.p);
+        Kp[rt][t] = Kh;
+      });
+    });
+  };
+
+  if (T0 < T1) {
+    auto tc = [&](int64_t T) { return T < T1 ? T : T1 - 1; };
+    Stage s0 = gload(T0);
+    sstore(s0, 0);
+    Stage s1 = gload(tc(T0 + 1));
+    __syncthreads();
+    int64_t T = T0;
+    for (; T + 1 < T1; T += 2) {
+      s0 = gload(tc(T + 2));
+      asm volatile("" ::: "memory");
+      compute(0);
+      sstore(s1, 1);
+      __syncthreads();
+      s1 = gload(tc(T + 3));
+      asm volatile("" ::: "memory");
+      compute(1);
+      sstore(s0, 0);
+      __syncthreads();
+    }
+    if (T < T1) compute(0);
+  }
+  kz_deferred();
+
+  // partial sums: lane l, register r is right-hand side 32 q + 8 (r / 4) + 4 g + r % 4 of
+  // row 32 rt + l % 32
+  static_for<2>([&](auto rc) {
+    constexpr int rt = decltype(rc)::value;
+    const int64_t row = row_base + rt * 32 + lane % 32;
+    if (row < a.m) {
+      static_for<NQW>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int rhs = q * 32 + 8 * (r / 4) + 4 * g + r % 4;
+          if (rhs < a.k) out[row * a.k + rhs] = acc[rt][q][r];
+        }
+      });
+    }
+  });
+}
+
+template <int KS, int NS, int KERN, int NQW>
+__global__ __launch_bounds__(256, 2) void mkw_kernel(MkArgs a) {
+  constexpr int TOTAL16 = 2 * KS * 64 + NQW * 2 * 64;
+  __shared__ __attribute__((aligned(16))) char lds[2 * ((TOTAL16 + 255) / 256) * 256 * 16];
+  const int bid = blockIdx.x;
+  const int prob = blockIdx.y;
+  int split, rw;
+  if (a.xcd_map) {
+    const int per = (int)gridDim.x / 8;
+    const int item = (bid % 8) * per + bid / 8;
+    split = item / a.rwg;
+    rw = item % a.rwg;
+  } else {
+    split = bid / a.rwg;
+    rw = bid % a.rwg;
+  }
+  const int64_t T0 = (int64_t)split * a.tiles_per_split;
+  int64_t T1 = T0 + a.tiles_per_split;
+  if (T1 > a.ntiles) T1 = a.ntiles;
+  mkw_tiles<KS, NS, KERN, NQW>(
+      a, lds, a.colA + prob * a.bs_colA, static_cast<const char*>(a.rhs) + prob * a.bs_rhs,
+      a.ridx ? a.ridx + prob * a.bs_ridx : nullptr, rw, T0, T1,
+      a.part + prob * a.bs_part + (int64_t)split * a.m * a.k);
+}
+
 // Persistent work-queue form for a batch of problems with uneven column counts: each
 // workgroup takes (problem, row workgroup, tile range) items from a global counter until the
 // table is exhausted; item i writes its partial sums to part[i][rows of its workgroup][k].
@@ -772,6 +1038,30 @@ void disp_mode_grid(const MkArgs& a, int mode, int nq, dim3 grid, hipStream_t s)
   }
 }
 
+template <int KS, int NS, int KERN>
+void launch_wide(const MkArgs& a, int nqw, int grid, hipStream_t s) {
+  if (nqw == 1) hipLaunchKernelGGL((mkw_kernel<KS, NS, KERN, 1>), dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((mkw_kernel<KS, NS, KERN, 2>), dim3(grid), dim3(256), 0, s, a);
+}
+
+template <int KS, int NS>
+void launch_wide_kern(const MkArgs& a, int kern, int nqw, int grid, hipStream_t s) {
+  switch (kern) {
+    case ADASAP_RBF: launch_wide<KS, NS, ADASAP_RBF>(a, nqw, grid, s); break;
+    case ADASAP_MATERN12: launch_wide<KS, NS, ADASAP_MATERN12>(a, nqw, grid, s); break;
+    case ADASAP_MATERN32: launch_wide<KS, NS, ADASAP_MATERN32>(a, nqw, grid, s); break;
+    default: launch_wide<KS, NS, ADASAP_MATERN52>(a, nqw, grid, s); break;
+  }
+}
+
+adasap_status_t disp_wide(const MkArgs& a, int ks, int ns, int kern, int nqw, int grid,
+                          hipStream_t s) {
+  if (ks == 1) launch_wide_kern<1, 2>(a, kern, nqw, grid, s);
+  else if (ns == 3) launch_wide_kern<2, 3>(a, kern, nqw, grid, s);
+  else launch_wide_kern<2, 4>(a, kern, nqw, grid, s);
+  return ADASAP_OK;
+}
+
 inline int ksteps(int d) { return 3 * d + 6 <= 32 ? 1 : 2; }
 
 double sigma_for(int kern, double ell) {
@@ -846,8 +1136,15 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
   const int grid = rwg * splits;
   const int KS = ks_force ? ks_force : ksteps(d);
   if (ev0) ADASAP_HIP(hipEventRecord(ev0, s));
-  if (KS == 1) ADASAP_TRY(disp_kern<1>(a, kern, rd.mode, rd.nq, grid, s));
-  else ADASAP_TRY(disp_kern<2>(a, kern, rd.mode, rd.nq, grid, s));
+  if (rd.mode == MODE_F16W) {
+    // K-slices of 16 for the 3d + 6 distance slots: 2 (d <= 8), 3 (d <= 14) or 4
+    const int ns = KS == 1 ? 2 : (3 * d + 6 <= 48 ? 3 : 4);
+    ADASAP_TRY(disp_wide(a, KS, ns, kern, rd.nq, grid, s));
+  } else if (KS == 1) {
+    ADASAP_TRY(disp_kern<1>(a, kern, rd.mode, rd.nq, grid, s));
+  } else {
+    ADASAP_TRY(disp_kern<2>(a, kern, rd.mode, rd.nq, grid, s));
+  }
   ADASAP_LAUNCH_CHECK();
   if (ev1) ADASAP_HIP(hipEventRecord(ev1, s));
   hipLaunchKernelGGL(mk_reduce_kernel, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, s,
@@ -878,9 +1175,11 @@ adasap_status_t pack_rhs(const void* R, DT rt, int64_t rows, int k, int64_t ldr,
     rd.scale = nullptr;
     return ADASAP_OK;
   }
-  const int nq = (k + 15) / 16;
+  const bool wide = mode == MODE_F16W;
+  // wide tiles: one or two blocks of 32 right-hand sides; otherwise tiles of 16
+  const int nq = wide ? (k <= 32 ? 1 : 2) : (k + 15) / 16;
   const int parts = mode == MODE_F16X3 ? 2 : 1;
-  ADASAP_TRY(buf.ensure((size_t)ntiles * nq * parts * 64 * 16));
+  ADASAP_TRY(buf.ensure((size_t)ntiles * nq * (wide ? 2 : parts) * 64 * 16));
   ADASAP_TRY(scale.ensure((size_t)k * sizeof(float)));
   // column maxima of the (gathered) right-hand side
   const int64_t rpb = colmax_rows_per_block(rows);
@@ -899,10 +1198,16 @@ adasap_status_t pack_rhs(const void* R, DT rt, int64_t rows, int k, int64_t ldr,
   hipLaunchKernelGGL(colmax_final_kernel, dim3(k), dim3(256), 0, s, tmp.as<float>(), nblk, k,
                      scale.as<float>());
   ADASAP_LAUNCH_CHECK();
-  const int64_t tot = ntiles * nq * 64;
-  hipLaunchKernelGGL(rhspack16_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R, rt,
-                     rows, k, ldr, nullptr, scale.as<float>(), ntiles, nq, parts,
-                     buf.as<half8>());
+  if (wide) {
+    const int64_t tot = ntiles * nq * 128;
+    hipLaunchKernelGGL(rhspackw_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R,
+                       rt, rows, k, ldr, scale.as<float>(), ntiles, nq, buf.as<half8>());
+  } else {
+    const int64_t tot = ntiles * nq * 64;
+    hipLaunchKernelGGL(rhspack16_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R,
+                       rt, rows, k, ldr, nullptr, scale.as<float>(), ntiles, nq, parts,
+                       buf.as<half8>());
+  }
   ADASAP_LAUNCH_CHECK();
   rd.nq = nq;
   rd.p = buf.p;
@@ -1013,6 +1318,9 @@ adasap_status_t mfma_product(const MfmaPack& pk, const int64_t* ridx, int64_t m,
   const bool all_cols = colsB == nullptr;
   const int64_t nt = all_cols ? pk.ntiles : (ncols + TILE - 1) / TILE;
   const int64_t rows = all_cols ? pk.n : ncols;
+  // the float16 mode with 17 to 64 right-hand sides runs on 32x32x16 MFMAs (more would not
+  // fit two waves per SIMD without scratch)
+  if (mode == MODE_F16 && k > 16 && k <= 64) mode = MODE_F16W;
   RhsDesc rd;
   ADASAP_TRY(pack_rhs(R, rt, rows, k, k, nullptr, nt, mode, w.rhs, w.scale, w.tmp, rd, s));
   if (w.wait_ev) ADASAP_HIP(hipStreamWaitEvent(s, w.wait_ev, 0));
