@@ -55,10 +55,10 @@ PEAK_F16_MFMA_TFLOPS = 2500.0
 # transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 8 lanes per clock x 2.4 GHz
 PEAK_EXP_TPS = 256 * 4 * 8 * 2.4e9 / 1e12
 # HBM bytes of one Step-I launch at the 2M-point, 64-column shape: rocprofv3 FETCH_SIZE and
-# WRITE_SIZE of the launch (7.637e5 and 2.867e4 KiB), each scaled by the ratio of true to
+# WRITE_SIZE of the launch (1.062e6 and 2.867e4 KiB), each scaled by the ratio of true to
 # counted KiB of a 1 GiB copy in the same run (2.0 for FETCH_SIZE, which prices the 128-byte
-# reads of gfx950 at 64 bytes, and 1.0 for WRITE_SIZE); profiles/mk_kernel_rbf_n2m_d11_k64.md
-STEP1_TRAFFIC_BYTES_N2M = 1.593e9
+# reads of gfx950 at 64 bytes, and 1.0 for WRITE_SIZE); profiles/mkw_kernel_rbf_n2m_d11_k64.md
+STEP1_TRAFFIC_BYTES_N2M = 2.203e9
 
 
 def log(msg):
@@ -174,7 +174,7 @@ def main():
                      "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_F16_MFMA_TFLOPS, 4),
                      "traffic": STEP1_TRAFFIC_BYTES_N2M if n == 2_000_000 else None,
-                     "kernel": "mk_kernel (step-I kernel-block product)",
+                     "kernel": "mkw_kernel (Step-I kernel-block product, float16 32x32x16 MFMA)",
                      "kernel_ms": round(kern_ms, 4),
                      "algorithmic_flops_per_launch": flops_step1},
         "cpu_baseline": cpu,

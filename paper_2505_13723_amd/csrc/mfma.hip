@@ -17,7 +17,8 @@
 // The eight kernel values of a lane (two column halves) form the B operand of the next MFMA
 // directly (K index = column slot), so the kernel block never leaves registers; the right-hand
 // side tile is stored pre-permuted in the matching slot order.
-//   MODE_F16   K and R in float16, one MFMA per (row tile, 16 right-hand sides)
+//   MODE_F16   K and R in float16, one MFMA per (row tile, 16 right-hand sides); with 17 to
+//              64 right-hand sides the same product runs on 32x32x16 MFMAs (MODE_F16W, below)
 //   MODE_F16X3 K = K_hi + K_lo and R = R_hi + R_lo, three MFMAs (hi.hi + lo.hi + hi.lo)
 //   MODE_F32V  K in float32 times float32 R on the vector ALUs (k <= 4)
 // The column range is split over workgroups; partial sums are added in a fixed order.
