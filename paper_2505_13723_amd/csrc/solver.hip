@@ -72,6 +72,10 @@ struct adasap_handle_s {
   hipStream_t s2 = nullptr;         // second stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_sketch = nullptr;   // the sketch of the current block is complete
+  hipEvent_t ev_bup = nullptr;      // the current block's indices are on the device
+  DevBuf Bslot[2];                  // device indices of the blocks of iterations t and t + 1
+  int64_t head_t = -1;              // iteration whose head is enqueued on s2 (-1: none)
+  uint64_t head_off = 0;
   DevBuf colsB;   // column fragments of the current block
   DevBuf rowq;    // row vectors of prediction points
   int64_t* Bhost[2] = {nullptr, nullptr};
@@ -90,6 +94,7 @@ struct adasap_handle_s {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_sketch) (void)hipEventDestroy(ev_sketch);
+    if (ev_bup) (void)hipEventDestroy(ev_bup);
     if (s2) (void)hipStreamDestroy(s2);
     for (int i = 0; i < 2; ++i) {
       if (Bhost[i]) (void)hipHostFree(Bhost[i]);
@@ -197,14 +202,24 @@ adasap_status_t block_gradient_h(adasap_handle_t h, const int64_t* B, const void
                    h->part_kb);
 }
 
-// The head of the second stream's chain for block B: its column fragments (or gathered
-// rows), Omega_t and the sketch K_{BB} Omega_t (Step II); ev_sketch marks the sketch.
-adasap_status_t iter_head(adasap_handle_t h, const int64_t* B, int64_t t, uint64_t off) {
+// The head of iteration t, on the second stream: the block B_t (host Floyd -> pinned slot ->
+// device slot t mod 2), its column fragments (or gathered rows), Omega_t and the sketch
+// K_{B_t B_t} Omega_t (Step II).  None of it depends on the iterate, so the previous
+// iteration enqueues it behind its own chain, to overlap its update; ev_bup marks the
+// indices on the device and ev_sketch the sketch.
+adasap_status_t iter_head(adasap_handle_t h, int64_t t, uint64_t off) {
   const adasap_config_t& c = h->cfg;
-  const int64_t b = c.block_size;
+  const int64_t n = h->n, b = c.block_size;
   const int r = c.rank, d = h->d;
   const int kprec = c.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
   hipStream_t s2 = h->s2;
+  const int slot = (int)(t & 1);
+  ADASAP_HIP(hipEventSynchronize(h->bev[slot]));
+  sample_block_host(c.seed, PURPOSE_B + off, (uint64_t)t, n, b, h->Bhost[slot]);
+  int64_t* B = h->Bslot[slot].as<int64_t>();
+  ADASAP_HIP(hipMemcpyAsync(B, h->Bhost[slot], b * sizeof(int64_t), hipMemcpyHostToDevice, s2));
+  ADASAP_HIP(hipEventRecord(h->bev[slot], s2));
+  ADASAP_HIP(hipEventRecord(h->ev_bup, s2));
   if (h->use_mfma) ADASAP_TRY(mfma_pack_block(h->pack, B, b, h->colsB, s2));
   else ADASAP_TRY(gather_rows(b, d, h->X, h->dtype, d, B, h->XB.p, h->dtype, d, s2));
   if (c.precond == ADASAP_PRECOND_NYSTROM) {
@@ -218,12 +233,15 @@ adasap_status_t iter_head(adasap_handle_t h, const int64_t* B, int64_t t, uint64
                            h->Ysk.p, DT::F64, r, none, kprec, s2, h->part_kb2));
     ADASAP_HIP(hipEventRecord(h->ev_sketch, s2));
   }
+  h->head_t = t;
+  h->head_off = off;
   return ADASAP_OK;
 }
 
-// one ADASAP iteration; rhs is the current right-hand side (Y or a refinement residual)
+// one ADASAP iteration; rhs is the current right-hand side (Y or a refinement residual);
+// with prefetch_next the head of iteration t + 1 is enqueued behind this iteration's chain
 adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* rhs, DT rhst,
-                        void* Wout) {
+                        void* Wout, bool prefetch_next) {
   const adasap_config_t& c = h->cfg;
   const int64_t n = h->n, b = c.block_size;
   const int k = h->k, r = c.rank;
@@ -233,22 +251,20 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   const int kprec = prec == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
   const bool nys = c.precond == ADASAP_PRECOND_NYSTROM;
 
-  // Step I: block B_t (host Floyd -> pinned slot -> device)
-  const int slot = (int)(t & 1);
-  ADASAP_HIP(hipEventSynchronize(h->bev[slot]));
-  sample_block_host(c.seed, PURPOSE_B + off, (uint64_t)t, n, b, h->Bhost[slot]);
-  ADASAP_HIP(hipMemcpyAsync(h->Bdev.p, h->Bhost[slot], b * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  ADASAP_HIP(hipEventRecord(h->bev[slot], s));
-  const int64_t* B = h->Bdev.as<int64_t>();
   // The sketch, the Nystrom factors and the step size do not depend on the block gradient:
-  // they run on a second stream while the main stream evaluates K_{B,:} Z.  The head of that
-  // chain, the sketch, is a matrix-core product that would compete with Step I, so it runs
-  // first with the whole GPU (the main stream packs Z meanwhile) and the Step-I product
-  // waits for it; the rest of the chain, mostly small kernels, runs beside Step I.
+  // they run on a second stream while the main stream evaluates K_{B,:} Z.  That stream
+  // rewrites the factors and scalars the previous update read, so it first waits for the
+  // main stream's work so far; the head of this iteration (block, sketch) may already be
+  // queued before the wait.  The sketch is a matrix-core product that would compete with
+  // Step I, so the Step-I product waits for it (the main stream packs Z meanwhile); the rest
+  // of the chain, mostly small kernels, runs beside Step I.
   hipStream_t s2 = h->s2;
   ADASAP_HIP(hipEventRecord(h->ev_fork, s));
   ADASAP_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
-  ADASAP_TRY(iter_head(h, B, t, off));
+  if (h->head_t != t || h->head_off != off) ADASAP_TRY(iter_head(h, t, off));
+  h->head_t = -1;
+  const int64_t* B = h->Bslot[t & 1].as<int64_t>();
+  ADASAP_HIP(hipStreamWaitEvent(s, h->ev_bup, 0));
   const bool sketch_first = nys && h->use_mfma;
 
   // gradient block at Z (accelerated; the reading of Alg. 2 Step IV), at W_t (accelerated,
@@ -339,6 +355,7 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   // join: the direction needs both the block gradient and the Nystrom factors
   ADASAP_HIP(hipEventRecord(h->ev_join, s2));
   ADASAP_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
+  if (prefetch_next) ADASAP_TRY(iter_head(h, t + 1, off));
   // Step IV: direction and update
   const double* Dp = h->G.as<double>();
   if (nys) {
@@ -439,7 +456,7 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
       ADASAP_HIP(hipEventRecord(e0, h->s));
       seg_open = true;
     }
-    ADASAP_TRY(iterate(h, t, off, rhs, rhst, need_w || !c.accel ? W : nullptr));
+    ADASAP_TRY(iterate(h, t, off, rhs, rhst, need_w || !c.accel ? W : nullptr, t + 1 < T));
     if (trace_pos < h->sc_host_cap) {
       ADASAP_HIP(hipMemcpyAsync(h->sc_host + trace_pos, h->scb.p, sizeof(IterScalars),
                                 hipMemcpyDeviceToHost, h->s));
@@ -454,6 +471,8 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
       check_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
       if (!std::isfinite(relres)) {
         set_error("non-finite residual");
+        (void)hipStreamSynchronize(h->s2);
+        h->head_t = -1;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         return ADASAP_ERR_NONFINITE;
@@ -466,6 +485,9 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
   if (tail && tail_count > 0)
     ADASAP_TRY(scale_store(nk, h->tail.as<double>(), 1.0 / (double)tail_count, W, h->dtype, h->s));
   ADASAP_HIP(hipStreamSynchronize(h->s));
+  // a head enqueued for an iteration that did not run (converged) is finished and dropped
+  ADASAP_HIP(hipStreamSynchronize(h->s2));
+  h->head_t = -1;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return ADASAP_OK;
@@ -559,6 +581,8 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   ENS(V, n * k * ss);
   ENS(Z, n * k * ss);
   ENS(Bdev, b * 8);
+  ENS(Bslot[0], b * 8);
+  ENS(Bslot[1], b * 8);
   ENS(XB, b * d * dt_size(h->dtype));
   ENS(G, b * k * 8);
   ENS(D, b * k * 8);
@@ -595,6 +619,7 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
       hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_sketch, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_bup, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking) != hipSuccess) {
     set_error("event creation failed");
     return fail(ADASAP_ERR_DEVICE);
