@@ -29,8 +29,11 @@ def abs_bound(Xr, Xc, R, kind, ell):
 
 
 @pytest.mark.parametrize("kind", list(KINDS))
+# k = 17..64 runs on the 32x32x16 (wide) form: (5, 40) takes two distance K-slices, (9, 17),
+# (11, 64) and (14, 33) three (3d + 6 = 48 at d = 14), (16, 64) four; the rest use the 16x16 form
 @pytest.mark.parametrize("m,n,d,k", [(300, 1000, 3, 1), (257, 641, 8, 3), (64, 2000, 9, 17),
-                                     (100, 333, 16, 64), (33, 77, 1, 100), (513, 4096, 11, 64)])
+                                     (100, 333, 16, 64), (33, 77, 1, 100), (513, 4096, 11, 64),
+                                     (130, 500, 5, 40), (200, 1000, 14, 33)])
 def test_mixed_kblock_matches_oracle(lib, kind, m, n, d, k):
     r0 = np.random.default_rng(m + 3 * n + d + k)
     Xr, Xc = r0.standard_normal((m, d)), r0.standard_normal((n, d))
