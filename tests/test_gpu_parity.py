@@ -235,3 +235,28 @@ def test_nonfinite_inputs_are_rejected(lib):
     with pytest.raises(AdasapError) as e:
         h.solve(W)
     assert e.value.status == 5
+
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+def test_solve_after_early_exit_matches_fresh_handle(lib, precision):
+    """Each iteration enqueues the next one's block and sketch ahead of time, so a solve that
+    stops on its tolerance leaves such a head behind.  A second solve on the same handle must
+    not use it: it repeats the first bit for bit and equals the solve on a fresh handle."""
+    X, Y = inputs.make_small(61, 900, 4, 20)
+    Xd, Yd = dev(X, torch.float32), dev(Y, torch.float32)
+    cfg = lib.config(kernel="rbf", lengthscale=1.0, lam=0.05, block_size=128, rank=32, seed=5,
+                     precision=precision, max_iters=40, tol=0.5, check_every=3)
+    h = lib.create(cfg, Xd, Yd)
+    W1 = torch.zeros_like(Yd)
+    rep1 = h.solve(W1)
+    W2 = torch.zeros_like(Yd)
+    rep2 = h.solve(W2)
+    h.close()
+    g = lib.create(cfg, Xd, Yd)
+    W3 = torch.zeros_like(Yd)
+    g.solve(W3)
+    g.close()
+    assert 0 < rep1["iters"] < 40, rep1["iters"]  # stopped early, the next head queued
+    assert rep2["iters"] == rep1["iters"]
+    assert torch.equal(W1, W2) and torch.equal(W1, W3)
