@@ -542,7 +542,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
 }
 
 // V = J_1 J_2 ... applied to the identity: ACC_ROWS rows of V per workgroup, one thread per
-// (row, pair); the rotations of one sweep are staged in LDS at a time.
+// (row, pair); the rotations of ACC_STEPS steps are staged in LDS at a time.  Rows are
+// independent, so workgroup barriers are needed only around the staging.
 constexpr int ACC_ROWS_MAX = 16;
 // threads per row of V: the rotation pairs (r/2), rounded up to 16, 32 or 64
 __host__ __device__ inline int acc_threads_per_row(int r) {
@@ -594,7 +595,10 @@ __global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* 
           Vs[ir][q] = s * vp + c * vq;
         }
       }
-      __syncthreads();
+      // the threads of one row of V lie in one wave (threads per row divide 64), and the next
+      // step reads only that row, written by that wave, whose LDS operations take effect in
+      // program order: a compiler barrier is enough between steps
+      asm volatile("" ::: "memory");
     }
   }
   __syncthreads();
