@@ -40,12 +40,17 @@ typedef enum {
   ADASAP_ERR_DEVICE = 3,        /* a HIP runtime call failed */
   ADASAP_ERR_NOT_PD = 4,        /* Nystrom core not positive definite after shift retries */
   ADASAP_ERR_NONFINITE = 5,     /* NaN/Inf in inputs or iterates */
-  ADASAP_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+  ADASAP_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement */
+  ADASAP_ERR_NOT_CONVERGED = 7  /* tol > 0 and the last checked relative residual is above it;
+                                   W holds the returned iterate and the report is filled */
 } adasap_status_t;
 
-/* Covariance functions (textbook forms, unit output scale, scalar lengthscale ell):
+/* Covariance functions (textbook forms; the paper names RBF and Matern kernels, Sec. 5):
  * RBF exp(-r^2/(2 ell^2)); Matern-1/2 exp(-r/ell); Matern-3/2 (1+a)e^{-a}, a = sqrt(3) r/ell;
- * Matern-5/2 (1+a+a^2/3)e^{-a}, a = sqrt(5) r/ell. */
+ * Matern-5/2 (1+a+a^2/3)e^{-a}, a = sqrt(5) r/ell.  With one lengthscale per coordinate (the
+ * fitted hyperparameters of the paper's regression experiments, appendix) the distance is
+ * r^2 = sum_j ((x_j - x'_j)/ell_j)^2 and the forms are taken at ell = 1.  An output scale s
+ * multiplies the kernel: K = s k(X, X). */
 typedef enum { ADASAP_RBF = 0, ADASAP_MATERN12 = 1, ADASAP_MATERN32 = 2, ADASAP_MATERN52 = 3 } adasap_kernel_t;
 
 /* Arithmetic of the kernel-block products.
@@ -87,6 +92,13 @@ typedef struct {
   int32_t grad_at_z;      /* 1: block gradient at Z_t (reading of Alg. 2 Step IV); 0: at W_t */
   int32_t z_uses_v_next;  /* 1: Z_{t+1} = alpha V_{t+1} + (1-alpha) W_{t+1}; 0: uses V_t */
   int32_t tail_average;   /* 1: return the mean of W_j, j = floor(T/2) .. T-1 */
+  int32_t n_lengthscale;  /* 0 or 1: the scalar `lengthscale`; d: per-coordinate lengthscales */
+  const double* lengthscales; /* host, d entries > 0 when n_lengthscale == d (copied by
+                                 adasap_create; unused otherwise, may be NULL) */
+  double outputscale;     /* s > 0: K = s k(X, X) (default 1) */
+  int64_t check_rows;     /* residual checks of a solve: 0 = all n rows; m > 0 = the
+                             row-subsampled estimate of adasap_residual_rows on min(m, n) rows
+                             (rows drawn with the configuration's seed) */
 } adasap_config_t;
 
 typedef struct {
@@ -111,10 +123,13 @@ typedef struct adasap_handle_s* adasap_handle_t;
  * 10 power iterations, Nystrom preconditioner, Nesterov on, FP32). */
 adasap_status_t adasap_config_default(adasap_config_t* cfg);
 
-/* Creates a solver for (K + lambda I) W = Y.  X (n x d) and Y (n x k) are device
+/* Creates a solver for (K + lambda I) W = Y (Sec. 2: the linear system behind the posterior
+ * mean and pathwise samples), K = outputscale * k(X, X).  X (n x d) and Y (n x k) are device
  * pointers of element type `dtype`; the handle borrows them (they must stay alive
  * and unchanged until adasap_destroy) and allocates its own device workspace
- * (adasap_workspace_bytes).  Requires 1 <= d <= 64 (d <= 16 for MIXED), 1 <= k <= 128.
+ * (adasap_workspace_bytes); with per-coordinate lengthscales that includes a float64 copy
+ * of X with coordinate j divided by ell_j, on which every kernel value is then computed.
+ * Requires 1 <= d <= 64 (d <= 16 for MIXED), 1 <= k <= 128.
  * On success *out receives the handle. */
 adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, int32_t k,
                               const void* X, const void* Y, int32_t dtype, void* stream,
@@ -123,10 +138,29 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
 /* Device bytes adasap_create would allocate for this problem (0 on invalid input). */
 int64_t adasap_workspace_bytes(const adasap_config_t* cfg, int64_t n, int32_t d, int32_t k);
 
-/* Runs the solve.  W (device, n x k, handle dtype) holds W_0 on entry (zeros =
- * cold start; V_0 = Z_0 = W_0) and the returned iterate on exit.  `report`
- * (host, may be NULL) receives statistics.  Synchronises the stream. */
+/* Runs the solve: ADASAP (Sec. 4, Alg. 2) for max_iters iterations, each sampling B_t,
+ * forming the block gradient at the extrapolated point Z_t, the Nystrom preconditioner of
+ * K_BB + rho I (Alg. NysApprox), the step size by powering (Alg. GetStepsize) and the
+ * Nesterov step (Alg. NestAcc); then `refine_sweeps` float64 refinement sweeps.  W (device,
+ * n x k, handle dtype) holds W_0 on entry (zeros = cold start; V_0 = Z_0 = W_0) and the
+ * returned iterate on exit.  With tol > 0 the relative residual is checked every
+ * check_every iterations and at the end, and the solve stops at the first check <= tol;
+ * if the last check is above tol the status is ADASAP_ERR_NOT_CONVERGED (W and the report
+ * are still filled).  `report` (host, may be NULL) receives statistics.  Synchronises the
+ * stream. */
 adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report);
+
+/* Continues the last adasap_solve of this handle for `iters` more iterations of the same
+ * run: the iteration counter, the random streams (B_t, Omega_t, v_t for t = T, T + 1, ...)
+ * and the Nesterov state (V_T, Z_T, kept by the handle) carry on, so a solve of T1
+ * iterations continued by T2 equals one solve of T1 + T2 iterations bit for bit (residual
+ * checks change nothing).  tol and check_every apply as in adasap_solve, counted from the
+ * continuation.  W (device, n x k) receives W_{T + iters}.  Requires a preceding solve
+ * without refinement sweeps and without tail averaging, and iters >= 1;
+ * ADASAP_ERR_INVALID_ARG otherwise (nothing is run).  `report` covers the continuation;
+ * its `iters` counts the iterations of this call.  Synchronises the stream. */
+adasap_status_t adasap_solve_more(adasap_handle_t h, void* W, int64_t iters,
+                                  adasap_report_t* report);
 
 /* Posterior mean m(X*) = k(X*, X) W (Sec. 2, Eq. post_eqns, zero prior mean).
  * W (device, n x k), Xstar (device, m x d), out (device, m x k), all handle dtype. */
@@ -146,6 +180,19 @@ adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres
  * (host) may be NULL; rows_out (device int64[m]) may be NULL.  Synchronises the stream. */
 adasap_status_t adasap_residual_rows(adasap_handle_t h, const void* W, int64_t m, uint64_t seed,
                                      double* relres, double* relres_maxcol, int64_t* rows_out);
+
+/* Certificate of a reduced-precision solve (Sec. 2: the system whose solution gives the
+ * posterior mean; residual in float64): the row-subsampled relative residual of
+ * adasap_residual_rows (same rows for the same seed), with every kernel value and product
+ * in float64 on the vector ALUs whatever the handle's precision (the coordinates are the
+ * handle's X, in its dtype, converted exactly to float64).  rel_se (host, may be NULL)
+ * receives the standard error of the estimate relative to it: the ratio estimator
+ * sum_S a_i / sum_S c_i (a_i = |r_i|^2, c_i = |y_i|^2) has variance (1 - m/n) s^2 / (m cbar^2)
+ * with s^2 the sample variance of a_i - Rhat c_i, and the square root halves the relative
+ * error.  Synchronises the stream. */
+adasap_status_t adasap_residual_rows_f64(adasap_handle_t h, const void* W, int64_t m,
+                                         uint64_t seed, double* relres, double* relres_maxcol,
+                                         double* rel_se, int64_t* rows_out);
 
 /* The block gradient of Step I of Alg. 2 at a caller-given point:
  * G = K(X_B, X) Z + lambda Z[B] - Y[B], where B = B_t is the block adasap_solve samples at

@@ -55,8 +55,9 @@ def nesterov_constants(mu, nu):
 def adasap(X, Y, kind, ell, lam, b, r, iters, seed, *, W0=None, rho_rule=0, rho=None,
            mu=None, nu=None, power_iters=10, precond="nystrom", accel=True,
            grad_at_z=True, z_uses_v_next=True, tail_average=False, eps_sketch=nys.EPS64,
-           sweep=0, callback=None):
-    """Run `iters` ADASAP iterations on (K + lam I) W = Y; returns (W, info)."""
+           sweep=0, callback=None, outputscale=1.0):
+    """Run `iters` ADASAP iterations on (K + lam I) W = Y; returns (W, info).  K is
+    outputscale * k(X, X); ell is a scalar or one lengthscale per coordinate."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
     squeeze = Y.ndim == 1
@@ -84,8 +85,8 @@ def adasap(X, Y, kind, ell, lam, b, r, iters, seed, *, W0=None, rho_rule=0, rho=
         B = rng.sample_block(seed, t, n, b, purpose=rng.PURPOSE_B + off)
         XB = X[B]
         P_at = Z if (accel and grad_at_z) else W
-        G = kmod.kernel_matmul(XB, X, P_at, kind, ell) + lam * P_at[B] - Y[B]
-        KBB = kmod.kernel_matrix(XB, XB, kind, ell)
+        G = kmod.kernel_matmul(XB, X, P_at, kind, ell, outputscale=outputscale) + lam * P_at[B] - Y[B]
+        KBB = kmod.kernel_matrix(XB, XB, kind, ell, outputscale=outputscale)
         v0 = rng.normals(seed, rng.PURPOSE_POW + off, t, b)
         if precond == "nystrom":
             # Step II: Gaussian test matrix, row i <-> B[i]
@@ -139,3 +140,82 @@ def adasap(X, Y, kind, ell, lam, b, r, iters, seed, *, W0=None, rho_rule=0, rho=
     info = {"eta": np.array(etas), "rho": np.array(rhos), "lambda_hat": np.array(lam_hats),
             "beta": beta, "gamma": gamma, "alpha": alpha, "V": V, "Z": Z}
     return (out[:, 0] if squeeze else out), info
+
+
+def adasap_from_zero(X, Y, kind, ell, lam, b, r, iters, seed, *, rho_rule=0, rho=None, mu=None,
+                     nu=None, power_iters=10, eps_sketch=nys.EPS64, log=None, outputscale=1.0):
+    """ADASAP (Alg. 2 with NestAcc, default readings) from W_0 = 0, on the touched rows only.
+
+    Started from zero, an iterate row changes only when its index is sampled: the all-rows
+    part of the Nesterov step maps a zero row of (V, Z) to zero, and the block part moves
+    only the rows of B_t.  So W_t, V_t and Z_t vanish outside S_t = B_0 u ... u B_{t-1}, and
+    Step I's product K(X_B, X) Z_t equals K(X_B, X_S) Z_t[S] exactly; it is evaluated that
+    way, which makes the first iterations of problems with millions of points affordable.
+    Every other step is that of adasap() with the same random streams.
+
+    Returns (S, W_S, info): the ascending touched rows, W_T on them, and the per-iteration
+    eta, rho and Rayleigh quotients.
+    """
+    X = np.asarray(X)
+    Y = np.asarray(Y)
+    if Y.ndim == 1:
+        Y = Y[:, None]
+    n, k = Y.shape
+    mu = lam if mu is None else mu
+    nu = n / b if nu is None else nu
+    beta, gamma, alpha = nesterov_constants(mu, nu)
+    S = np.zeros(0, dtype=np.int64)
+    W = np.zeros((0, k))
+    V = np.zeros((0, k))
+    Z = np.zeros((0, k))
+    etas, rhos, lam_hats = [], [], []
+    for t in range(iters):
+        B = rng.sample_block(seed, t, n, b, purpose=rng.PURPOSE_B)
+        XB = np.asarray(X[B], dtype=np.float64)
+        # Z_t on the block rows (zero where the row was never touched)
+        ZB = np.zeros((b, k))
+        if S.size:
+            pos = np.minimum(np.searchsorted(S, B), S.size - 1)
+            hit = S[pos] == B
+            ZB[hit] = Z[pos[hit]]
+        # Step I on the touched columns
+        KZ = kmod.kernel_matmul(XB, np.asarray(X[S], dtype=np.float64), Z, kind, ell,
+                                outputscale=outputscale) if S.size else np.zeros((b, k))
+        G = KZ + lam * ZB - np.asarray(Y[B], dtype=np.float64)
+        # Steps II and III
+        KBB = kmod.kernel_matrix(XB, XB, kind, ell, outputscale=outputscale)
+        Omega = rng.normals(seed, rng.PURPOSE_OMEGA, t, b * r).reshape(b, r)
+        U, Sv, _delta = nys.nystrom(KBB @ Omega, Omega, eps=eps_sketch)
+        rho_t = lam + Sv[-1] if rho_rule == 0 else float(rho)
+        v0 = rng.normals(seed, rng.PURPOSE_POW, t, b)
+        eta, lam_hat = preconditioned_stepsize(
+            lambda v: KBB @ v + lam * v,
+            lambda v: nys.precond_inv_sqrt(U, Sv, rho_t, v), v0, power_iters)
+        D = nys.precond_inv(U, Sv, rho_t, G)
+        etas.append(eta)
+        rhos.append(rho_t)
+        lam_hats.append(lam_hat)
+        # Step IV on S_{t+1} = S_t u B_t (new rows enter as zeros)
+        S_new = np.union1d(S, B)
+        grow = lambda A: _scatter_rows(A, np.searchsorted(S_new, S), S_new.size)
+        W, V, Z = grow(W), grow(V), grow(Z)
+        step = np.zeros_like(W)
+        step[np.searchsorted(S_new, B)] = eta * D
+        W_next = Z - step
+        V_next = beta * V + (1.0 - beta) * Z - gamma * step
+        Z = alpha * V_next + (1.0 - alpha) * W_next
+        V = V_next
+        W = W_next
+        S = S_new
+        if log is not None:
+            log("oracle iteration %d of %d: |S| = %d, eta = %.6e, rho = %.6e" % (t + 1, iters, S.size,
+                                                                               eta, rho_t))
+    info = {"eta": np.array(etas), "rho": np.array(rhos), "lambda_hat": np.array(lam_hats),
+            "beta": beta, "gamma": gamma, "alpha": alpha}
+    return S, W, info
+
+
+def _scatter_rows(A, pos, m):
+    out = np.zeros((m, A.shape[1]))
+    out[pos] = A
+    return out

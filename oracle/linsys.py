@@ -46,23 +46,24 @@ def backward_subst(U, B):
     return X
 
 
-def direct_solve(X, Y, kind, ell, lam):
+def direct_solve(X, Y, kind, ell, lam, outputscale=1.0):
     """W* = (K + lambda I)^{-1} Y with the oracle's own Cholesky and substitutions."""
-    K = kmod.kernel_matrix(X, X, kind, ell)
+    K = kmod.kernel_matrix(X, X, kind, ell, outputscale=outputscale)
     A = K + lam * np.eye(K.shape[0])
     L = cholesky_lower(A)
     return backward_subst(L.T, forward_subst(L, np.asarray(Y, dtype=np.float64)))
 
 
-def residual(X, Y, W, kind, ell, lam):
+def residual(X, Y, W, kind, ell, lam, outputscale=1.0):
     """R = K W + lambda W - Y."""
     W = np.asarray(W, dtype=np.float64)
-    return kmod.kernel_matmul(X, X, W, kind, ell) + lam * W - np.asarray(Y, dtype=np.float64)
+    return (kmod.kernel_matmul(X, X, W, kind, ell, outputscale=outputscale) + lam * W
+            - np.asarray(Y, dtype=np.float64))
 
 
-def relres(X, Y, W, kind, ell, lam):
+def relres(X, Y, W, kind, ell, lam, outputscale=1.0):
     """(||R||_F / ||Y||_F, max over columns of ||R_c|| / ||Y_c||)."""
-    R = residual(X, Y, W, kind, ell, lam)
+    R = residual(X, Y, W, kind, ell, lam, outputscale)
     Y = np.asarray(Y, dtype=np.float64)
     fro = np.linalg.norm(R) / np.linalg.norm(Y)
     if R.ndim == 1:
@@ -71,14 +72,15 @@ def relres(X, Y, W, kind, ell, lam):
     return fro, float(cols.max())
 
 
-def residual_rows(X, Y, W, kind, ell, lam, rows):
+def residual_rows(X, Y, W, kind, ell, lam, rows, outputscale=1.0):
     """Rows `rows` of the residual, computed one row at a time against all n columns."""
     W = np.asarray(W, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
     rows = np.asarray(rows)
-    return kmod.kernel_matmul(X[rows], X, W, kind, ell) + lam * W[rows] - Y[rows]
+    return (kmod.kernel_matmul(X[rows], X, W, kind, ell, outputscale=outputscale) + lam * W[rows]
+            - Y[rows])
 
 
-def predict(Xstar, X, W, kind, ell):
+def predict(Xstar, X, W, kind, ell, outputscale=1.0):
     """Posterior mean m(X*) = k(X*, X) W (zero prior mean)."""
-    return kmod.kernel_matmul(Xstar, X, W, kind, ell)
+    return kmod.kernel_matmul(Xstar, X, W, kind, ell, outputscale=outputscale)

@@ -17,10 +17,13 @@ RBF, MATERN12, MATERN32, MATERN52 = 0, 1, 2, 3
 KERNELS = {"rbf": RBF, "matern12": MATERN12, "matern32": MATERN32, "matern52": MATERN52}
 FP64, FP32, MIXED = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
-PRECOND_NYSTROM, PRECOND_IDENTITY = 0, 1
+PRECOND_NYSTROM, PRECOND_IDENTITY, PRECOND_EXACT = 0, 1, 2
+PRECONDS = {"nystrom": PRECOND_NYSTROM, "identity": PRECOND_IDENTITY, "exact": PRECOND_EXACT}
 DTYPE_F32, DTYPE_F64 = 0, 1
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error",
-          4: "Nystrom core not positive definite", 5: "non-finite values", 6: "unsupported"}
+          4: "Nystrom core not positive definite", 5: "non-finite values", 6: "unsupported",
+          7: "not converged"}
+NOT_CONVERGED = 7
 
 # purposes of the random streams (second Philox key word)
 PURPOSE_B, PURPOSE_OMEGA, PURPOSE_POW, PURPOSE_SWEEP_STRIDE = 5, 6, 7, 16
@@ -43,6 +46,8 @@ class Config(ctypes.Structure):
         ("precond", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("accel", ctypes.c_int32), ("grad_at_z", ctypes.c_int32),
         ("z_uses_v_next", ctypes.c_int32), ("tail_average", ctypes.c_int32),
+        ("n_lengthscale", ctypes.c_int32), ("lengthscales", ctypes.POINTER(ctypes.c_double)),
+        ("outputscale", ctypes.c_double), ("check_rows", ctypes.c_int64),
     ]
 
 
@@ -84,11 +89,14 @@ _SIGNATURES = {
     "adasap_create": (_I32, [ctypes.POINTER(Config), _I64, _I32, _I32, _P, _P, _I32, _P, ctypes.POINTER(_P)]),
     "adasap_workspace_bytes": (_I64, [ctypes.POINTER(Config), _I64, _I32, _I32]),
     "adasap_solve": (_I32, [_P, _P, ctypes.POINTER(Report)]),
+    "adasap_solve_more": (_I32, [_P, _P, _I64, ctypes.POINTER(Report)]),
     "adasap_predict": (_I32, [_P, _P, _I64, _P, _P]),
     "adasap_residual": (_I32, [_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "adasap_get_trace": (_I32, [_P, _P, _P, _P, _I64]),
     "adasap_block_gradient": (_I32, [_P, _I64, _P, _P, _P]),
     "adasap_residual_rows": (_I32, [_P, _P, _I64, _U64, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
+    "adasap_residual_rows_f64": (_I32, [_P, _P, _I64, _U64, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                        ctypes.POINTER(_D), _P]),
     "adasap_destroy": (None, [_P]),
     "adasap_sample_block": (_I32, [_U64, _U64, _U64, _I64, _I64, _P]),
     "adasap_normals": (_I32, [_U64, _U64, _U64, _I64, _P, _P]),
@@ -182,8 +190,17 @@ class Library:
                 val = KERNELS[val]
             if key == "precision" and isinstance(val, str):
                 val = PRECISIONS[val]
+            if key == "precond" and isinstance(val, str):
+                val = PRECONDS[val]
             if key == "lambda":
                 key = "lam"
+            if key == "lengthscales":
+                # one lengthscale per coordinate: the array is kept with the config until
+                # adasap_create copies it
+                arr = (ctypes.c_double * len(val))(*[float(v) for v in val])
+                cfg._ell_keep = arr
+                cfg.n_lengthscale = len(val)
+                val = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
             if not hasattr(cfg, key):
                 raise KeyError(key)
             setattr(cfg, key, val)
@@ -372,10 +389,22 @@ class Handle:
         self.lib, self.h, self.X, self.Y, self.cfg = lib, h, X, Y, cfg
 
     def solve(self, W):
+        """Run the solve in place on W; returns the report.  A solve that ends above its
+        tolerance (status "not converged") returns its report too: report["status"] says so."""
         _check_dev(W)
         rep = Report()
         st = self.lib.cdll.adasap_solve(self.h, _ptr(W), ctypes.byref(rep))
-        self.lib.check(st)
+        if st != NOT_CONVERGED:
+            self.lib.check(st)
+        return rep.as_dict()
+
+    def solve_more(self, W, iters):
+        """Continue the last solve for `iters` iterations (same random streams and state)."""
+        _check_dev(W)
+        rep = Report()
+        st = self.lib.cdll.adasap_solve_more(self.h, _ptr(W), int(iters), ctypes.byref(rep))
+        if st != NOT_CONVERGED:
+            self.lib.check(st)
         return rep.as_dict()
 
     def predict(self, W, Xstar):
@@ -401,6 +430,16 @@ class Handle:
         self.lib.check(self.lib.cdll.adasap_residual_rows(self.h, _ptr(W), int(m), int(seed),
                                                           ctypes.byref(a), ctypes.byref(mx), _ptr(R)))
         return (a.value, mx.value, R) if rows else (a.value, mx.value)
+
+    def residual_rows_f64(self, W, m, seed):
+        """Row-subsampled relative residual with float64 kernel values and products:
+        (estimate, worst column, relative standard error)."""
+        _check_dev(W)
+        a, mx, se = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self.lib.check(self.lib.cdll.adasap_residual_rows_f64(self.h, _ptr(W), int(m), int(seed),
+                                                              ctypes.byref(a), ctypes.byref(mx),
+                                                              ctypes.byref(se), None))
+        return a.value, mx.value, se.value
 
     def block_gradient(self, t, Z):
         """(B_t, G) of Step I at iterate Z, through the solver's own Step-I launch."""

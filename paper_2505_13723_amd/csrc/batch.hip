@@ -77,6 +77,8 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
   if (cfg->max_iters < 0) return invalid("max_iters must be >= 0");
   if (cfg->rho_rule != 0 && cfg->rho_rule != 1) return invalid("rho_rule must be 0 or 1");
   if (cfg->rho_rule == 1 && !(cfg->rho > 0)) return invalid("rho must be > 0");
+  if (cfg->n_lengthscale > 1 || cfg->outputscale != 1.0)
+    return invalid("batched solves take one scalar lengthscale per problem and unit output scale");
   const int P = count;
   const int64_t b = cfg->block_size;
   const int r = cfg->rank;

@@ -40,7 +40,9 @@ constexpr int64_t SC_DOUBLES = sizeof(IterScalars) / sizeof(double);
 // arithmetic `prec` (FP64 or FP32 VALU path).  The sum over j is split into `splits`
 // column ranges whose partial results are added in a fixed order (deterministic).
 struct KbEpilogue {
-  // out = acc + a1 * E1[e1idx? e1idx[i] : i, c] + a2 * E2[...]; E pointers may be null.
+  // out = kscale * acc + a1 * E1[e1idx? e1idx[i] : i, c] + a2 * E2[...]; E pointers may be null.
+  // kscale is the kernel's output scale (K = kscale * k(X, X)).
+  double kscale = 1.0;
   const void* E1 = nullptr;
   DT e1t = DT::F64;
   const int64_t* e1idx = nullptr;
@@ -132,6 +134,9 @@ adasap_status_t gather_rows(int64_t rows, int cols, const void* src, DT st, int6
                             const int64_t* idx, void* dst, DT dt, int64_t ldd, hipStream_t s);
 // elementwise copy / convert of a dense n x k array
 adasap_status_t convert(int64_t count, const void* src, DT st, void* dst, DT dt, hipStream_t s);
+// out (n x d, float64) = X (type xt) with column j multiplied by scale[j] (device array)
+adasap_status_t scale_columns(int64_t n, int d, const void* X, DT xt, const double* scale,
+                              double* out, hipStream_t s);
 
 struct NestCoef {
   double beta, gamma, alpha;

@@ -91,6 +91,7 @@ __global__ void kblock_reduce_kernel(const TA* __restrict__ part, int splits, in
   const int c = (int)(e % k);
   double s = 0.0;
   for (int sp = 0; sp < splits; ++sp) s += (double)part[((int64_t)sp * m + i) * k + c];
+  s *= ep.kscale;
   if (ep.E1) s += ep.a1 * load_d(ep.E1, ep.e1t, (ep.e1idx ? ep.e1idx[i] : i) * ep.lde1 + c);
   if (ep.E2) s += ep.a2 * load_d(ep.E2, ep.e2t, (ep.e2idx ? ep.e2idx[i] : i) * ep.lde2 + c);
   if (ot == DT::F64) static_cast<double*>(out)[i * ldo + c] = s;
@@ -121,6 +122,49 @@ __global__ void colsq_final_kernel(const double* __restrict__ part, int nblk, in
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * k + c];
     out[c] = s;
+  }
+}
+
+// Sums over the rows of two rows x k float64 arrays A and C (row i: a_i = |A_i|^2,
+// c_i = |C_i|^2): {sum a, sum c, sum a^2, sum c^2, sum a c}, per block of CN_ROWS rows, then
+// added in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void ratio_stats_partial_kernel(const double* __restrict__ A,
+                                                                  const double* __restrict__ C,
+                                                                  int64_t rows, int k,
+                                                                  double* __restrict__ part) {
+  __shared__ double red[5][256];
+  const int64_t r0 = (int64_t)blockIdx.x * CN_ROWS;
+  const int64_t r1 = r0 + CN_ROWS < rows ? r0 + CN_ROWS : rows;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    double a = 0.0, c = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double x = A[r * k + j], y = C[r * k + j];
+      a += x * x;
+      c += y * y;
+    }
+    s[0] += a;
+    s[1] += c;
+    s[2] += a * a;
+    s[3] += c * c;
+    s[4] += a * c;
+  }
+  for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = s[q];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) part[(int64_t)blockIdx.x * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void ratio_stats_final_kernel(const double* __restrict__ part, int nblk,
+                                         double* __restrict__ out) {
+  if (threadIdx.x < 5) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * 5 + threadIdx.x];
+    out[threadIdx.x] = s;
   }
 }
 
@@ -173,6 +217,20 @@ adasap_status_t colsq(int64_t rows, int k, const void* a, DT t, int64_t lda, dou
     ADASAP_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(colsq_final_kernel, dim3(1), dim3(128), 0, s, tmp.as<double>(), nblk, k, out);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+adasap_status_t ratio_stats(int64_t rows, int k, const double* A, const double* C, double* out,
+                            DevBuf& tmp, hipStream_t s) {
+  const int nblk = (int)((rows + CN_ROWS - 1) / CN_ROWS);
+  ADASAP_TRY(tmp.ensure((size_t)(nblk > 0 ? nblk : 1) * 5 * sizeof(double)));
+  if (nblk > 0) {
+    hipLaunchKernelGGL(ratio_stats_partial_kernel, dim3(nblk), dim3(256), 0, s, A, C, rows, k,
+                       tmp.as<double>());
+    ADASAP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(ratio_stats_final_kernel, dim3(1), dim3(64), 0, s, tmp.as<double>(), nblk, out);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }

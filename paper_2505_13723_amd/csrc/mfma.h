@@ -70,7 +70,7 @@ adasap_status_t mfma_points(const MfmaPack& pk, const void* Xq, DT xt, int64_t m
 // OUT = K(Xq, X) R for query rows packed by mfma_points
 adasap_status_t mfma_product_rows(const MfmaPack& pk, const void* rowq, int64_t m, const void* R,
                                   DT rt, int k, int mode, void* out, DT ot, MfmaWork& w,
-                                  hipStream_t s);
+                                  hipStream_t s, double kscale = 1.0);
 
 // ---- batches of independent problems (all with two K-steps, d <= 16) --------------------------
 // Points of problem p occupy rows row_off[p] .. row_off[p] + ntiles[p]*32 of the global row

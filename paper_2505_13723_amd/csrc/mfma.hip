@@ -960,6 +960,7 @@ __global__ void mk_reduce_kernel(const float* __restrict__ part, int splits, int
   double s = 0.0;
   for (int sp = 0; sp < splits; ++sp) s += (double)part[((int64_t)sp * m + i) * k + c];
   if (scale) s *= (double)scale[c];
+  s *= ep.kscale;
   auto ld = [](const void* p, DT t, int64_t j) {
     return t == DT::F64 ? static_cast<const double*>(p)[j] : (double)static_cast<const float*>(p)[j];
   };
@@ -1371,12 +1372,13 @@ adasap_status_t mfma_points(const MfmaPack& pk, const void* Xq, DT xt, int64_t m
 
 adasap_status_t mfma_product_rows(const MfmaPack& pk, const void* rowq, int64_t m, const void* R,
                                   DT rt, int k, int mode, void* out, DT ot, MfmaWork& w,
-                                  hipStream_t s) {
+                                  hipStream_t s, double kscale) {
   RhsDesc rd;
   ADASAP_TRY(pack_rhs(R, rt, pk.n, k, k, nullptr, pk.ntiles, mode, w.rhs, w.scale, w.tmp, rd, s));
-  KbEpilogue none;
+  KbEpilogue ep;
+  ep.kscale = kscale;
   return mk_run(pk.cols.as<half8>(), pk.ntiles, static_cast<const half8*>(rowq), nullptr, m, pk.d,
-                pk.kern, rd, k, out, ot, none, w.part, s);
+                pk.kern, rd, k, out, ot, ep, w.part, s);
 }
 
 adasap_status_t mfma_batch_pack_create(MfmaBatchPack& bp, int P, const int64_t* n, const int* d,

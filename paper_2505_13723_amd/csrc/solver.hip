@@ -24,6 +24,8 @@ namespace adasap {
 
 adasap_status_t colsq(int64_t rows, int k, const void* a, DT t, int64_t lda, double* out,
                       DevBuf& tmp, hipStream_t s);
+adasap_status_t ratio_stats(int64_t rows, int k, const double* A, const double* C, double* out,
+                            DevBuf& tmp, hipStream_t s);
 
 adasap_status_t DevBuf::ensure(size_t want) {
   if (want <= bytes && p) return ADASAP_OK;
@@ -59,6 +61,13 @@ struct adasap_handle_s {
   hipStream_t s = nullptr;
   const void* X = nullptr;
   const void* Y = nullptr;
+  // coordinates every kernel value is computed from: X itself, or with per-coordinate
+  // lengthscales the owned float64 copy Xs (coordinate j divided by ell_j) at lengthscale 1
+  const void* Xk = nullptr;
+  DT xkt = DT::F32;
+  double ellk = 1.0;
+  std::vector<double> inv_ell;  // 1/ell_j (per-coordinate lengthscales only)
+  DevBuf Xs, Xq, iell;          // the scaled copy; scaled prediction points; 1/ell_j (device)
   double mu = 0, nu = 0;
   NestCoef nc{};
   bool use_mfma = false;
@@ -83,6 +92,9 @@ struct adasap_handle_s {
   IterScalars* sc_host = nullptr;  // pinned trace of per-iteration scalars
   int64_t sc_host_cap = 0;
   std::vector<double> eta_tr, rho_tr, lh_tr;
+  // iterations of the last plain solve whose state (V, Z) the handle still holds, so that
+  // adasap_solve_more can continue it (-1: nothing to continue)
+  int64_t t_done = -1;
   // ring of event pairs around the step-I product kernel; a pair is read back (long after it
   // completed) when the ring wraps, so no event is created inside the iteration loop
   static constexpr int KEV_RING = 32;
@@ -119,7 +131,17 @@ adasap_status_t validate(const adasap_config_t* c, int64_t n, int d, int k) {
   if (!c) return invalid("config is null");
   if (c->struct_size != sizeof(adasap_config_t)) return invalid("config struct_size mismatch");
   if (c->kernel < 0 || c->kernel > 3) return invalid("unknown kernel");
-  if (!finite_pos(c->lengthscale)) return invalid("lengthscale must be finite and > 0");
+  if (c->n_lengthscale != 0 && c->n_lengthscale != 1 && c->n_lengthscale != d)
+    return invalid("n_lengthscale must be 0, 1 or d");
+  if (c->n_lengthscale == d && d > 1) {
+    if (!c->lengthscales) return invalid("lengthscales must be a host array of d entries");
+    for (int j = 0; j < d; ++j)
+      if (!finite_pos(c->lengthscales[j])) return invalid("lengthscales must be finite and > 0");
+  } else if (!finite_pos(c->lengthscale)) {
+    return invalid("lengthscale must be finite and > 0");
+  }
+  if (!finite_pos(c->outputscale)) return invalid("outputscale must be finite and > 0");
+  if (c->check_rows < 0) return invalid("check_rows must be >= 0");
   if (!finite_pos(c->lambda)) return invalid("lambda must be finite and > 0");
   if (n < 1) return invalid("n must be >= 1");
   if (d < 1 || d > 64) return invalid("d must be in [1, 64]");
@@ -157,8 +179,10 @@ adasap_status_t hk_kblock(adasap_handle_t h, int64_t m, int64_t n, const void* X
                           const int64_t* ridx, DT xt, const void* Xc, const void* R, DT rt,
                           int64_t ldr, int kk, void* out, DT ot, int64_t ldo, const KbEpilogue& ep,
                           int prec, hipStream_t st, DevBuf& part) {
-  return kblock_valu(h->cfg.kernel, h->cfg.lengthscale, prec, m, n, h->d, kk, Xr, ridx, xt, Xc, R,
-                     rt, ldr, out, ot, ldo, ep, part, st);
+  KbEpilogue e = ep;
+  e.kscale = h->cfg.outputscale;
+  return kblock_valu(h->cfg.kernel, h->ellk, prec, m, n, h->d, kk, Xr, ridx, xt, Xc, R, rt, ldr, out,
+                     ot, ldo, e, part, st);
 }
 
 // P^{-1} X (power 0) or P^{-1/2} X (power 1) for the current Nystrom factors; X, out b x kk
@@ -182,6 +206,7 @@ adasap_status_t block_gradient_h(adasap_handle_t h, const int64_t* B, const void
   const int64_t n = h->n, b = c.block_size;
   const int k = h->k;
   KbEpilogue epg;
+  epg.kscale = c.outputscale;
   epg.E1 = gp;
   epg.e1t = gt;
   epg.e1idx = B;
@@ -198,7 +223,7 @@ adasap_status_t block_gradient_h(adasap_handle_t h, const int64_t* B, const void
     return mfma_product(h->pack, B, b, nullptr, 0, gp, gt, k, mode, G, DT::F64, epg, h->mw, s);
   }
   const int kprec = c.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
-  return hk_kblock(h, b, n, h->X, B, h->dtype, h->X, gp, gt, k, k, G, DT::F64, k, epg, kprec, s,
+  return hk_kblock(h, b, n, h->Xk, B, h->xkt, h->Xk, gp, gt, k, k, G, DT::F64, k, epg, kprec, s,
                    h->part_kb);
 }
 
@@ -221,15 +246,16 @@ adasap_status_t iter_head(adasap_handle_t h, int64_t t, uint64_t off) {
   ADASAP_HIP(hipEventRecord(h->bev[slot], s2));
   ADASAP_HIP(hipEventRecord(h->ev_bup, s2));
   if (h->use_mfma) ADASAP_TRY(mfma_pack_block(h->pack, B, b, h->colsB, s2));
-  else ADASAP_TRY(gather_rows(b, d, h->X, h->dtype, d, B, h->XB.p, h->dtype, d, s2));
+  else ADASAP_TRY(gather_rows(b, d, h->Xk, h->xkt, d, B, h->XB.p, h->xkt, d, s2));
   if (c.precond == ADASAP_PRECOND_NYSTROM) {
     ADASAP_TRY(normals_dev(c.seed, PURPOSE_OMEGA + off, (uint64_t)t, b * r, h->Om.as<double>(), s2));
     KbEpilogue none;
+    none.kscale = c.outputscale;
     if (h->use_mfma)
       ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, h->Om.p, DT::F64, r, mfma_mode_f16x3(),
                               h->Ysk.p, DT::F64, none, h->mw2, s2));
     else
-      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, h->Om.p, DT::F64, r, r,
+      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->xkt, h->XB.p, h->Om.p, DT::F64, r, r,
                            h->Ysk.p, DT::F64, r, none, kprec, s2, h->part_kb2));
     ADASAP_HIP(hipEventRecord(h->ev_sketch, s2));
   }
@@ -334,6 +360,7 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
       win = w;
     }
     KbEpilogue epp;
+    epp.kscale = c.outputscale;
     epp.E1 = win;
     epp.e1t = DT::F64;
     epp.lde1 = 1;
@@ -342,7 +369,7 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
       ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, win, DT::F64, 1, mfma_mode_f32v(), u,
                               DT::F64, epp, h->mw2, s2));
     else
-      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->dtype, h->XB.p, win, DT::F64, 1, 1, u,
+      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->xkt, h->XB.p, win, DT::F64, 1, 1, u,
                            DT::F64, 1, epp, kprec, s2, h->part_kb2));
     const double* zin = u;
     if (nys) {
@@ -375,6 +402,7 @@ adasap_status_t residual_h(adasap_handle_t h, const void* W, DT wt, const void* 
   ADASAP_TRY(h->res.ensure((size_t)n * k * sizeof(double)));
   ADASAP_TRY(h->colq.ensure(2 * (size_t)k * sizeof(double)));
   KbEpilogue ep;
+  ep.kscale = h->cfg.outputscale;
   ep.E1 = W;
   ep.e1t = wt;
   ep.lde1 = k;
@@ -392,7 +420,7 @@ adasap_status_t residual_h(adasap_handle_t h, const void* W, DT wt, const void* 
     h->mw.cap_cus = cap;
     ADASAP_TRY(pst);
   } else {
-    ADASAP_TRY(hk_kblock(h, n, n, h->X, nullptr, h->dtype, h->X, W, wt, k, k, h->res.p, DT::F64, k,
+    ADASAP_TRY(hk_kblock(h, n, n, h->Xk, nullptr, h->xkt, h->Xk, W, wt, k, k, h->res.p, DT::F64, k,
                          ep, ADASAP_FP64, h->s, h->part_kb));
   }
   double* cq = h->colq.as<double>();
@@ -414,10 +442,15 @@ adasap_status_t residual_h(adasap_handle_t h, const void* W, DT wt, const void* 
   return ADASAP_OK;
 }
 
+adasap_status_t residual_rows_h(adasap_handle_t h, const void* W, DT wt, const void* rhs, DT rhst,
+                                int64_t m, uint64_t seed, bool fp64, double* relres,
+                                double* relres_maxcol, double* rel_se, int64_t* rows_out);
+
 // solve (K + lambda I) Wst = rhs from the state already in (V, Z); writes W (handle dtype)
 adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT rhst, void* W,
-                          int64_t& iters_done, double& relres, double& relmax, double& solve_ms,
-                          double& check_ms, int64_t& trace_pos) {
+                          int64_t t0, int64_t T, int64_t& iters_done, double& relres,
+                          double& relmax, double& solve_ms, double& check_ms,
+                          int64_t& trace_pos) {
   const adasap_config_t& c = h->cfg;
   const int64_t nk = h->n * h->k;
   // device time of the iterations: one event pair per segment between residual checks;
@@ -443,20 +476,20 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
     ADASAP_TRY(h->tail.ensure((size_t)nk * sizeof(double)));
     ADASAP_HIP(hipMemsetAsync(h->tail.p, 0, (size_t)nk * sizeof(double), h->s));
   }
-  const int64_t T = c.max_iters;
   const int64_t every = (c.tol > 0) ? (c.check_every > 0 ? c.check_every : T) : 0;
-  for (int64_t t = 0; t < T; ++t) {
-    if (tail && t >= T / 2) {
+  for (int64_t i = 0; i < T; ++i) {
+    const int64_t t = t0 + i;
+    if (tail && i >= T / 2) {
       ADASAP_TRY(accumulate(nk, W, h->dtype, h->tail.as<double>(), h->s));
       ++tail_count;
     }
-    const bool check_now = every > 0 && ((t + 1) % every == 0 || t + 1 == T);
-    const bool need_w = tail || check_now || t + 1 == T || (c.accel && !c.grad_at_z);
+    const bool check_now = every > 0 && ((i + 1) % every == 0 || i + 1 == T);
+    const bool need_w = tail || check_now || i + 1 == T || (c.accel && !c.grad_at_z);
     if (!seg_open) {
       ADASAP_HIP(hipEventRecord(e0, h->s));
       seg_open = true;
     }
-    ADASAP_TRY(iterate(h, t, off, rhs, rhst, need_w || !c.accel ? W : nullptr, t + 1 < T));
+    ADASAP_TRY(iterate(h, t, off, rhs, rhst, need_w || !c.accel ? W : nullptr, i + 1 < T));
     if (trace_pos < h->sc_host_cap) {
       ADASAP_HIP(hipMemcpyAsync(h->sc_host + trace_pos, h->scb.p, sizeof(IterScalars),
                                 hipMemcpyDeviceToHost, h->s));
@@ -467,7 +500,11 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
     if (check_now) {
       ADASAP_TRY(close_segment());
       auto c0 = std::chrono::steady_clock::now();
-      ADASAP_TRY(residual_h(h, W, h->dtype, rhs, rhst, &relres, &relmax, false));
+      if (c.check_rows > 0)
+        ADASAP_TRY(residual_rows_h(h, W, h->dtype, rhs, rhst, c.check_rows < h->n ? c.check_rows : h->n,
+                                   c.seed, false, &relres, &relmax, nullptr, nullptr));
+      else
+        ADASAP_TRY(residual_h(h, W, h->dtype, rhs, rhst, &relres, &relmax, false));
       check_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
       if (!std::isfinite(relres)) {
         set_error("non-finite residual");
@@ -490,6 +527,155 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
   h->head_t = -1;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return ADASAP_OK;
+}
+
+// Row-subsampled relative residual: m rows S (Floyd on (seed, 12, 0)), each computed against
+// all n columns with the handle's products (matrix-core hi/lo or float64) or, with fp64, with
+// float64 kernel values and products; optionally the relative standard error of the ratio
+// estimate (delta method, finite-population corrected).
+adasap_status_t residual_rows_h(adasap_handle_t h, const void* W, DT wt, const void* rhs, DT rhst,
+                                int64_t m, uint64_t seed, bool fp64, double* relres,
+                                double* relres_maxcol, double* rel_se, int64_t* rows_out) {
+  if (!h) return invalid("handle is null");
+  if (!W) return invalid("W must be a non-null device pointer");
+  if (m < 1 || m > h->n) return invalid("m must be in [1, n]");
+  const int64_t n = h->n;
+  const int k = h->k;
+  std::vector<int64_t> rows((size_t)m);
+  sample_block_host(seed, PURPOSE_RESROWS, 0, n, m, rows.data());
+  DevBuf rdev, yrows, stats;
+  ADASAP_TRY(rdev.ensure((size_t)m * sizeof(int64_t)));
+  ADASAP_TRY(yrows.ensure((size_t)m * k * sizeof(double)));
+  ADASAP_TRY(stats.ensure(5 * sizeof(double)));
+  ADASAP_TRY(h->res.ensure((size_t)m * k * sizeof(double)));
+  ADASAP_TRY(h->colq.ensure(2 * (size_t)k * sizeof(double)));
+  ADASAP_HIP(hipMemcpyAsync(rdev.p, rows.data(), (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
+  const int64_t* ridx = rdev.as<int64_t>();
+  KbEpilogue ep;
+  ep.kscale = h->cfg.outputscale;
+  ep.E1 = W;
+  ep.e1t = wt;
+  ep.e1idx = ridx;
+  ep.lde1 = k;
+  ep.a1 = h->cfg.lambda;
+  ep.E2 = rhs;
+  ep.e2t = rhst;
+  ep.e2idx = ridx;
+  ep.lde2 = k;
+  ep.a2 = -1.0;
+  if (h->use_mfma && !fp64) {
+    const int cap = h->mw.cap_cus;
+    h->mw.cap_cus = 0;
+    const adasap_status_t pst = mfma_product(h->pack, ridx, m, nullptr, 0, W, wt, k,
+                                             mfma_mode_f16x3(), h->res.p, DT::F64, ep, h->mw, h->s);
+    h->mw.cap_cus = cap;
+    ADASAP_TRY(pst);
+  } else {
+    ADASAP_TRY(hk_kblock(h, m, n, h->Xk, ridx, h->xkt, h->Xk, W, wt, k, k, h->res.p, DT::F64, k, ep,
+                         ADASAP_FP64, h->s, h->part_kb));
+  }
+  ADASAP_TRY(gather_rows(m, k, rhs, rhst, k, ridx, yrows.p, DT::F64, k, h->s));
+  double* cq = h->colq.as<double>();
+  ADASAP_TRY(colsq(m, k, h->res.p, DT::F64, k, cq, h->tmp, h->s));
+  ADASAP_TRY(colsq(m, k, yrows.p, DT::F64, k, cq + k, h->tmp, h->s));
+  std::vector<double> hq(2 * (size_t)k);
+  double st[5] = {0, 0, 0, 0, 0};
+  ADASAP_HIP(hipMemcpyAsync(hq.data(), cq, 2 * (size_t)k * sizeof(double), hipMemcpyDeviceToHost, h->s));
+  if (rel_se) {
+    ADASAP_TRY(ratio_stats(m, k, h->res.as<double>(), yrows.as<double>(), stats.as<double>(), h->tmp,
+                           h->s));
+    ADASAP_HIP(hipMemcpyAsync(st, stats.p, 5 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+  }
+  if (rows_out)
+    ADASAP_HIP(hipMemcpyAsync(rows_out, ridx, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToDevice, h->s));
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  double rs = 0, ys = 0, mx = 0;
+  for (int c = 0; c < k; ++c) {
+    rs += hq[c];
+    ys += hq[k + c];
+    const double col = hq[k + c] > 0 ? std::sqrt(hq[c] / hq[k + c]) : std::sqrt(hq[c]);
+    mx = col > mx ? col : mx;
+  }
+  if (relres) *relres = ys > 0 ? std::sqrt(rs / ys) : std::sqrt(rs);
+  if (relres_maxcol) *relres_maxcol = mx;
+  if (rel_se) {
+    // Rhat = sum a / sum c; s^2 = sum (a - Rhat c)^2 / (m - 1); Var(Rhat) = (1 - m/n) s^2 / (m cbar^2)
+    const double A = st[0], C = st[1];
+    double se = 0.0;
+    if (m > 1 && A > 0 && C > 0) {
+      const double R = A / C;
+      const double ss = st[2] - 2.0 * R * st[4] + R * R * st[3];
+      const double s2 = (ss > 0 ? ss : 0.0) / (double)(m - 1);
+      const double cbar = C / (double)m;
+      const double var = (1.0 - (double)m / (double)n) * s2 / ((double)m * cbar * cbar);
+      se = 0.5 * std::sqrt(var) / R;
+    }
+    *rel_se = se;
+  }
+  return ADASAP_OK;
+}
+
+// pinned trace of per-iteration scalars for `iters` iterations
+adasap_status_t ensure_trace(adasap_handle_t h, int64_t iters) {
+  if (h->sc_host_cap >= iters) return ADASAP_OK;
+  if (h->sc_host) (void)hipHostFree(h->sc_host);
+  h->sc_host = nullptr;
+  h->sc_host_cap = 0;
+  if (iters > 0) {
+    if (hipHostMalloc((void**)&h->sc_host, iters * sizeof(IterScalars)) != hipSuccess) {
+      set_error("pinned host allocation failed");
+      return ADASAP_ERR_OOM;
+    }
+    h->sc_host_cap = iters;
+  }
+  return ADASAP_OK;
+}
+
+// fills the report from the per-iteration trace and the timing ring of the finished run
+adasap_status_t finish_report(adasap_handle_t h, adasap_report_t& rep, int64_t trace_pos,
+                              double relres, double relmax) {
+  const adasap_config_t& c = h->cfg;
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  const int64_t ntr = trace_pos < h->sc_host_cap ? trace_pos : h->sc_host_cap;
+  h->eta_tr.resize(ntr);
+  h->rho_tr.resize(ntr);
+  h->lh_tr.resize(ntr);
+  for (int64_t i = 0; i < ntr; ++i) {
+    h->eta_tr[i] = h->sc_host[i].eta;
+    h->rho_tr[i] = h->sc_host[i].rho;
+    h->lh_tr[i] = h->sc_host[i].lam_hat;
+    rep.not_pd_events += h->sc_host[i].not_pd;
+    if (h->sc_host[i].sweeps > rep.jacobi_sweeps_max) rep.jacobi_sweeps_max = h->sc_host[i].sweeps;
+    if (h->sc_host[i].failed) {
+      set_error("Nystrom core not positive definite after shift retries");
+      rep.status = ADASAP_ERR_NOT_PD;
+    }
+  }
+  if (ntr > 0) {
+    rep.eta_last = h->eta_tr[ntr - 1];
+    rep.rho_last = h->rho_tr[ntr - 1];
+    rep.lambda_hat_last = h->lh_tr[ntr - 1];
+    rep.delta_last = h->sc_host[ntr - 1].delta;
+  }
+  rep.relres = relres;
+  rep.relres_maxcol = relmax;
+  {
+    const int ring = adasap_handle_s::KEV_RING;
+    const int64_t pending = h->kev_used < ring ? h->kev_used : ring;
+    rep.step1_kernel_ms = h->step1_ms;
+    for (int64_t i = 0; i < pending; ++i) {
+      const int slot = (int)((h->kev_used - 1 - i) % ring);
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, h->kev[2 * slot], h->kev[2 * slot + 1]) == hipSuccess)
+        rep.step1_kernel_ms += ms;
+    }
+  }
+  rep.step1_launches = h->kev_used;
+  if (rep.status == ADASAP_OK && c.tol > 0 && !(relres >= 0 && relres <= c.tol)) {
+    set_error("relative residual " + std::to_string(relres) + " above tol " + std::to_string(c.tol));
+    rep.status = ADASAP_ERR_NOT_CONVERGED;
+  }
   return ADASAP_OK;
 }
 
@@ -526,6 +712,10 @@ adasap_status_t adasap_config_default(adasap_config_t* cfg) {
   cfg->grad_at_z = 1;
   cfg->z_uses_v_next = 1;
   cfg->tail_average = 0;
+  cfg->n_lengthscale = 0;
+  cfg->lengthscales = nullptr;
+  cfg->outputscale = 1.0;
+  cfg->check_rows = 0;
   return ADASAP_OK;
 }
 
@@ -537,6 +727,7 @@ int64_t adasap_workspace_bytes(const adasap_config_t* cfg, int64_t n, int32_t d,
   bytes += b * (8 + 8 * d + 16 * k + 24 * r + 32);      // B, X_B, G, D, Omega, Y_sk, B, U, vectors
   bytes += 8 * r * r * 8 + 8 * (int64_t)jacobi_rot_capacity((int)r);
   if (cfg->precision != ADASAP_FP64 && d <= 16) bytes += mfma_pack_bytes(n, d, k);
+  if (cfg->n_lengthscale == d && d > 1) bytes += n * d * 8;  // scaled copy of X
   return bytes;
 }
 
@@ -559,6 +750,9 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   h->s = static_cast<hipStream_t>(stream);
   h->X = X;
   h->Y = Y;
+  h->Xk = X;
+  h->xkt = h->dtype;
+  h->ellk = cfg->lengthscale;
   h->mu = cfg->mu > 0 ? cfg->mu : cfg->lambda;
   h->nu = cfg->nu > 0 ? cfg->nu : (double)n / (double)cfg->block_size;
   h->nc.beta = 1.0 - std::sqrt(h->mu / h->nu);
@@ -580,10 +774,15 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   if ((st = h->buf.ensure((size_t)(bytes))) != ADASAP_OK) return fail(st)
   ENS(V, n * k * ss);
   ENS(Z, n * k * ss);
+  const bool ard = cfg->n_lengthscale == d && d > 1;
+  if (ard) {
+    ENS(Xs, (size_t)n * d * 8);
+    ENS(iell, (size_t)d * 8);
+  }
   ENS(Bdev, b * 8);
   ENS(Bslot[0], b * 8);
   ENS(Bslot[1], b * 8);
-  ENS(XB, b * d * dt_size(h->dtype));
+  ENS(XB, b * d * (ard ? 8 : dt_size(h->dtype)));
   ENS(G, b * k * 8);
   ENS(D, b * k * 8);
   ENS(Om, b * r * 8);
@@ -625,6 +824,21 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
     return fail(ADASAP_ERR_DEVICE);
   }
   if (hipMemsetAsync(h->scb.p, 0, sizeof(IterScalars), h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
+  if (ard) {
+    // per-coordinate lengthscales: every kernel value is computed from x_j / ell_j at ell = 1
+    h->inv_ell.resize(d);
+    for (int j = 0; j < d; ++j) h->inv_ell[j] = 1.0 / cfg->lengthscales[j];
+    h->cfg.lengthscales = nullptr;  // the caller's array is not kept
+    if (hipMemcpyAsync(h->iell.p, h->inv_ell.data(), (size_t)d * 8, hipMemcpyHostToDevice, h->s) !=
+        hipSuccess)
+      return fail(ADASAP_ERR_DEVICE);
+    if ((st = scale_columns(n, d, X, h->dtype, h->iell.as<double>(), h->Xs.as<double>(), h->s)) !=
+        ADASAP_OK)
+      return fail(st);
+    h->Xk = h->Xs.p;
+    h->xkt = DT::F64;
+    h->ellk = 1.0;
+  }
   if (h->use_mfma) {
     // the Step-I product runs as one resident round on 7/8 of the workgroup slots, so that
     // the second stream's sketch, Nystrom and powering kernels find room
@@ -632,7 +846,7 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
       h->mw.cap_cus = cus;
-    st = mfma_pack_create(h->pack, n, d, k, X, h->dtype, cfg->kernel, cfg->lengthscale, h->s);
+    st = mfma_pack_create(h->pack, n, d, k, h->Xk, h->xkt, cfg->kernel, h->ellk, h->s);
     if (st == ADASAP_ERR_UNSUPPORTED && cfg->precision == ADASAP_FP32) {
       h->use_mfma = false;  // coordinates outside the float16 range: vector-ALU products
     } else if (st != ADASAP_OK) {
@@ -653,6 +867,7 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
   std::memset(&rep, 0, sizeof(rep));
   rep.relres = -1;
   rep.relres_maxcol = -1;
+  h->t_done = -1;
   int nf = 0;
   ADASAP_TRY(any_nonfinite(h->n * h->d, h->X, h->dtype, &nf, h->tmp, h->s));
   if (!nf) ADASAP_TRY(any_nonfinite(nk, h->Y, h->dtype, &nf, h->tmp, h->s));
@@ -661,19 +876,7 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
     set_error("X, Y or W0 contains NaN or Inf");
     return ADASAP_ERR_NONFINITE;
   }
-  const int64_t total_iters = c.max_iters * (1 + c.refine_sweeps);
-  if (h->sc_host_cap < total_iters) {
-    if (h->sc_host) (void)hipHostFree(h->sc_host);
-    h->sc_host = nullptr;
-    h->sc_host_cap = 0;
-    if (total_iters > 0) {
-      if (hipHostMalloc((void**)&h->sc_host, total_iters * sizeof(IterScalars)) != hipSuccess) {
-        set_error("pinned host allocation failed");
-        return ADASAP_ERR_OOM;
-      }
-      h->sc_host_cap = total_iters;
-    }
-  }
+  ADASAP_TRY(ensure_trace(h, c.max_iters * (1 + c.refine_sweeps)));
   // V_0 = Z_0 = W_0
   ADASAP_TRY(convert(nk, W, h->dtype, h->V.p, h->st, h->s));
   ADASAP_TRY(convert(nk, W, h->dtype, h->Z.p, h->st, h->s));
@@ -681,8 +884,8 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
   h->kev_used = 0;
   h->step1_ms = 0;
   double relres = -1, relmax = -1;
-  ADASAP_TRY(run_sweep(h, 0, h->Y, h->dtype, W, rep.iters, relres, relmax, rep.solve_ms,
-                       rep.check_ms, trace_pos));
+  ADASAP_TRY(run_sweep(h, 0, h->Y, h->dtype, W, 0, c.max_iters, rep.iters, relres, relmax,
+                       rep.solve_ms, rep.check_ms, trace_pos));
   // float64 iterative refinement: R = Y - (K + lambda I) W, solve for the correction, add it
   for (int sw = 1; sw <= c.refine_sweeps; ++sw) {
     ADASAP_TRY(h->rhs.ensure((size_t)nk * sizeof(double)));
@@ -696,7 +899,7 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
     ADASAP_HIP(hipMemsetAsync(h->Z.p, 0, (size_t)nk * dt_size(h->st), h->s));
     double r2 = -1, m2 = -1;
     ADASAP_TRY(run_sweep(h, PURPOSE_SWEEP_STRIDE * (uint64_t)sw, h->rhs.p, DT::F64, h->delta_w.p,
-                         rep.iters, r2, m2, rep.solve_ms, rep.check_ms, trace_pos));
+                         0, c.max_iters, rep.iters, r2, m2, rep.solve_ms, rep.check_ms, trace_pos));
     ADASAP_TRY(add_inplace(nk, W, h->dtype, h->delta_w.p, h->dtype, h->s));
     rep.refine_done = sw;
     relres = -1;
@@ -706,42 +909,35 @@ adasap_status_t adasap_solve(adasap_handle_t h, void* W, adasap_report_t* report
     ADASAP_TRY(residual_h(h, W, h->dtype, h->Y, h->dtype, &relres, &relmax, false));
     rep.check_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
   }
-  ADASAP_HIP(hipStreamSynchronize(h->s));
-  const int64_t ntr = trace_pos < h->sc_host_cap ? trace_pos : h->sc_host_cap;
-  h->eta_tr.resize(ntr);
-  h->rho_tr.resize(ntr);
-  h->lh_tr.resize(ntr);
-  for (int64_t i = 0; i < ntr; ++i) {
-    h->eta_tr[i] = h->sc_host[i].eta;
-    h->rho_tr[i] = h->sc_host[i].rho;
-    h->lh_tr[i] = h->sc_host[i].lam_hat;
-    rep.not_pd_events += h->sc_host[i].not_pd;
-    if (h->sc_host[i].sweeps > rep.jacobi_sweeps_max) rep.jacobi_sweeps_max = h->sc_host[i].sweeps;
-    if (h->sc_host[i].failed) {
-      set_error("Nystrom core not positive definite after shift retries");
-      rep.status = ADASAP_ERR_NOT_PD;
-    }
-  }
-  if (ntr > 0) {
-    rep.eta_last = h->eta_tr[ntr - 1];
-    rep.rho_last = h->rho_tr[ntr - 1];
-    rep.lambda_hat_last = h->lh_tr[ntr - 1];
-    rep.delta_last = h->sc_host[ntr - 1].delta;
-  }
-  rep.relres = relres;
-  rep.relres_maxcol = relmax;
-  {
-    const int ring = adasap_handle_s::KEV_RING;
-    const int64_t pending = h->kev_used < ring ? h->kev_used : ring;
-    rep.step1_kernel_ms = h->step1_ms;
-    for (int64_t i = 0; i < pending; ++i) {
-      const int slot = (int)((h->kev_used - 1 - i) % ring);
-      float ms = 0;
-      if (hipEventElapsedTime(&ms, h->kev[2 * slot], h->kev[2 * slot + 1]) == hipSuccess)
-        rep.step1_kernel_ms += ms;
-    }
-  }
-  rep.step1_launches = h->kev_used;
+  ADASAP_TRY(finish_report(h, rep, trace_pos, relres, relmax));
+  if (c.refine_sweeps == 0 && !c.tail_average) h->t_done = rep.iters;
+  if (report) *report = rep;
+  return rep.status == ADASAP_OK ? ADASAP_OK : (adasap_status_t)rep.status;
+}
+
+adasap_status_t adasap_solve_more(adasap_handle_t h, void* W, int64_t iters,
+                                  adasap_report_t* report) {
+  if (!h) return invalid("handle is null");
+  if (!W) return invalid("W must be a non-null device pointer");
+  if (iters < 1) return invalid("iters must be >= 1");
+  if (h->t_done < 0)
+    return invalid("no solve to continue (none run yet, or it used refinement sweeps or tail "
+                   "averaging, or failed)");
+  adasap_report_t rep;
+  std::memset(&rep, 0, sizeof(rep));
+  rep.relres = -1;
+  rep.relres_maxcol = -1;
+  const int64_t t0 = h->t_done;
+  h->t_done = -1;
+  ADASAP_TRY(ensure_trace(h, iters));
+  int64_t trace_pos = 0;
+  h->kev_used = 0;
+  h->step1_ms = 0;
+  double relres = -1, relmax = -1;
+  ADASAP_TRY(run_sweep(h, 0, h->Y, h->dtype, W, t0, iters, rep.iters, relres, relmax, rep.solve_ms,
+                       rep.check_ms, trace_pos));
+  ADASAP_TRY(finish_report(h, rep, trace_pos, relres, relmax));
+  h->t_done = t0 + rep.iters;
   if (report) *report = rep;
   return rep.status == ADASAP_OK ? ADASAP_OK : (adasap_status_t)rep.status;
 }
@@ -754,13 +950,22 @@ adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, cons
   if (!W || !Xstar || !out) return invalid("W, Xstar and out must be non-null device pointers");
   KbEpilogue none;
   const int kprec = h->cfg.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
+  // prediction points in the coordinates the kernel values are computed from
+  const void* Xq = Xstar;
+  DT xqt = h->dtype;
+  if (!h->inv_ell.empty()) {
+    ADASAP_TRY(h->Xq.ensure((size_t)m * h->d * 8));
+    ADASAP_TRY(scale_columns(m, h->d, Xstar, h->dtype, h->iell.as<double>(), h->Xq.as<double>(), h->s));
+    Xq = h->Xq.p;
+    xqt = DT::F64;
+  }
   if (h->use_mfma) {
-    ADASAP_TRY(mfma_points(h->pack, Xstar, h->dtype, m, h->rowq, h->s));
+    ADASAP_TRY(mfma_points(h->pack, Xq, xqt, m, h->rowq, h->s));
     ADASAP_TRY(mfma_product_rows(h->pack, h->rowq.p, m, W, h->dtype, h->k, mfma_mode_f16x3(), out,
-                                 h->dtype, h->mw, h->s));
+                                 h->dtype, h->mw, h->s, h->cfg.outputscale));
   } else {
-    ADASAP_TRY(hk_kblock(h, m, h->n, Xstar, nullptr, h->dtype, h->X, W, h->dtype, h->k, h->k, out,
-                         h->dtype, h->k, none, kprec, h->s, h->part_kb));
+    ADASAP_TRY(hk_kblock(h, m, h->n, Xq, nullptr, xqt, h->Xk, W, h->dtype, h->k, h->k, out, h->dtype,
+                         h->k, none, kprec, h->s, h->part_kb));
   }
   ADASAP_HIP(hipStreamSynchronize(h->s));
   return ADASAP_OK;
@@ -776,60 +981,16 @@ adasap_status_t adasap_residual(adasap_handle_t h, const void* W, double* relres
 adasap_status_t adasap_residual_rows(adasap_handle_t h, const void* W, int64_t m, uint64_t seed,
                                      double* relres, double* relres_maxcol, int64_t* rows_out) {
   if (!h) return invalid("handle is null");
-  if (!W) return invalid("W must be a non-null device pointer");
-  if (m < 1 || m > h->n) return invalid("m must be in [1, n]");
-  const int64_t n = h->n;
-  const int k = h->k;
-  std::vector<int64_t> rows((size_t)m);
-  sample_block_host(seed, PURPOSE_RESROWS, 0, n, m, rows.data());
-  DevBuf rdev, yrows;
-  ADASAP_TRY(rdev.ensure((size_t)m * sizeof(int64_t)));
-  ADASAP_TRY(yrows.ensure((size_t)m * k * sizeof(double)));
-  ADASAP_TRY(h->res.ensure((size_t)m * k * sizeof(double)));
-  ADASAP_TRY(h->colq.ensure(2 * (size_t)k * sizeof(double)));
-  ADASAP_HIP(hipMemcpyAsync(rdev.p, rows.data(), (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
-  const int64_t* ridx = rdev.as<int64_t>();
-  KbEpilogue ep;
-  ep.E1 = W;
-  ep.e1t = h->dtype;
-  ep.e1idx = ridx;
-  ep.lde1 = k;
-  ep.a1 = h->cfg.lambda;
-  ep.E2 = h->Y;
-  ep.e2t = h->dtype;
-  ep.e2idx = ridx;
-  ep.lde2 = k;
-  ep.a2 = -1.0;
-  if (h->use_mfma) {
-    const int cap = h->mw.cap_cus;
-    h->mw.cap_cus = 0;
-    const adasap_status_t pst = mfma_product(h->pack, ridx, m, nullptr, 0, W, h->dtype, k,
-                                             mfma_mode_f16x3(), h->res.p, DT::F64, ep, h->mw, h->s);
-    h->mw.cap_cus = cap;
-    ADASAP_TRY(pst);
-  } else {
-    ADASAP_TRY(hk_kblock(h, m, n, h->X, ridx, h->dtype, h->X, W, h->dtype, k, k, h->res.p, DT::F64,
-                         k, ep, ADASAP_FP64, h->s, h->part_kb));
-  }
-  ADASAP_TRY(gather_rows(m, k, h->Y, h->dtype, k, ridx, yrows.p, DT::F64, k, h->s));
-  double* cq = h->colq.as<double>();
-  ADASAP_TRY(colsq(m, k, h->res.p, DT::F64, k, cq, h->tmp, h->s));
-  ADASAP_TRY(colsq(m, k, yrows.p, DT::F64, k, cq + k, h->tmp, h->s));
-  std::vector<double> hq(2 * (size_t)k);
-  ADASAP_HIP(hipMemcpyAsync(hq.data(), cq, 2 * (size_t)k * sizeof(double), hipMemcpyDeviceToHost, h->s));
-  if (rows_out)
-    ADASAP_HIP(hipMemcpyAsync(rows_out, ridx, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToDevice, h->s));
-  ADASAP_HIP(hipStreamSynchronize(h->s));
-  double rs = 0, ys = 0, mx = 0;
-  for (int c = 0; c < k; ++c) {
-    rs += hq[c];
-    ys += hq[k + c];
-    const double col = hq[k + c] > 0 ? std::sqrt(hq[c] / hq[k + c]) : std::sqrt(hq[c]);
-    mx = col > mx ? col : mx;
-  }
-  if (relres) *relres = ys > 0 ? std::sqrt(rs / ys) : std::sqrt(rs);
-  if (relres_maxcol) *relres_maxcol = mx;
-  return ADASAP_OK;
+  return residual_rows_h(h, W, h->dtype, h->Y, h->dtype, m, seed, false, relres, relres_maxcol,
+                         nullptr, rows_out);
+}
+
+adasap_status_t adasap_residual_rows_f64(adasap_handle_t h, const void* W, int64_t m,
+                                         uint64_t seed, double* relres, double* relres_maxcol,
+                                         double* rel_se, int64_t* rows_out) {
+  if (!h) return invalid("handle is null");
+  return residual_rows_h(h, W, h->dtype, h->Y, h->dtype, m, seed, true, relres, relres_maxcol,
+                         rel_se, rows_out);
 }
 
 adasap_status_t adasap_block_gradient(adasap_handle_t h, int64_t t, const void* Z, int64_t* B_out,
@@ -995,6 +1156,7 @@ const char* adasap_status_string(adasap_status_t s) {
     case ADASAP_ERR_NOT_PD: return "Nystrom core not positive definite";
     case ADASAP_ERR_NONFINITE: return "non-finite values";
     case ADASAP_ERR_UNSUPPORTED: return "unsupported";
+    case ADASAP_ERR_NOT_CONVERGED: return "not converged";
     default: return "unknown status";
   }
 }

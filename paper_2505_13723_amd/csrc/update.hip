@@ -142,6 +142,25 @@ adasap_status_t gather_rows(int64_t rows, int cols, const void* src, DT st, int6
   return ADASAP_OK;
 }
 
+// out[i, j] = X[i, j] * scale[j] in float64 (per-coordinate lengthscales folded into the points)
+__global__ void scale_columns_kernel(int64_t n, int d, const void* __restrict__ X, DT xt,
+                                     const double* __restrict__ scale, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * d) return;
+  const double x = xt == DT::F64 ? static_cast<const double*>(X)[e]
+                                 : (double)static_cast<const float*>(X)[e];
+  out[e] = x * scale[e % d];
+}
+
+adasap_status_t scale_columns(int64_t n, int d, const void* X, DT xt, const double* scale,
+                              double* out, hipStream_t s) {
+  if (n * d <= 0) return ADASAP_OK;
+  hipLaunchKernelGGL(scale_columns_kernel, dim3(nblocks(n * d)), dim3(256), 0, s, n, d, X, xt, scale,
+                     out);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
 adasap_status_t convert(int64_t count, const void* src, DT st, void* dst, DT dt, hipStream_t s) {
   if (count <= 0) return ADASAP_OK;
   hipLaunchKernelGGL(convert_kernel, dim3(nblocks(count)), dim3(256), 0, s, count, src, st, dst, dt);

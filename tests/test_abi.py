@@ -25,7 +25,7 @@ def _declared_functions():
     inc = os.path.join(ROOT, "include")
     text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(adasap_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(adasap_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported(hlib):
@@ -43,7 +43,7 @@ def test_config_layout_and_defaults(hlib):
 
 
 def test_status_strings(hlib):
-    for code in range(7):
+    for code in range(8):
         assert hlib.cdll.adasap_status_string(code).decode()
 
 
@@ -51,6 +51,8 @@ def test_status_strings(hlib):
     ("lam", 0.0), ("lam", -1.0), ("lengthscale", 0.0), ("block_size", 0), ("block_size", 1001),
     ("rank", 0), ("rank", 129), ("rho_rule", 1), ("kernel", 9), ("precision", 7),
     ("power_iters", 0), ("mu", 1e6), ("refine_sweeps", 99), ("tol", -1.0), ("precond", 5),
+    ("outputscale", 0.0), ("outputscale", float("inf")), ("check_rows", -1), ("n_lengthscale", 2),
+    ("n_lengthscale", 4),
 ])
 def test_create_rejects_bad_config_before_device_work(hlib, field, value):
     kw = dict(block_size=100, rank=20)

@@ -1,0 +1,185 @@
+"""Trajectory parity of whole solves at the block sizes the benchmarks run.
+
+Two groups of cases, each run through adasap_solve and compared with the float64 oracle on
+the same seeded inputs and random streams (block B_t, Omega_t, powering start v_t):
+
+* mid-size: n = 40,000, d = 11, k = 20, b = 4096, r = 128, three iterations at FP64, FP32 and
+  MIXED against the dense oracle (oracle.adasap).  At b = 4096 the solver takes the paths the
+  large workloads take: the k <= 4 Woodbury applies of the powering loop reduce 64 row
+  splits with the tree reduction (more than 32 splits), the r x r Grams split 4096 rows,
+  and the Nystrom core factors a 4096 x 128 sketch.  MIXED with k = 20 runs Step I on the
+  32x32x16 form, FP32 with k = 20 on the float16 hi/lo form;
+* full size: the 2M-point RBF workload (d = 11, k = 64, b = 16384, r = 128, MIXED) and the
+  1M-point Matern-3/2 workload with near-duplicates (d = 11, k = 1, b = 8192, r = 100, FP32),
+  two iterations from W_0 = 0 against oracle.adasap_from_zero, which evaluates Step I on
+  the rows the iteration has touched (exact from a zero start).
+
+Compared: the step sizes eta_t and dampings rho_t of every iteration, and the relative
+residual difference delta = ||(K + lambda I)(W_gpu - W_oracle)||_F / ||Y||_F (the reading of
+"match the oracle within a relative residual"): at most 1e-6 for FP64 and 1e-3 for the
+reduced-precision paths.  The GPU iterate must also vanish outside the touched rows, as the
+oracle's does.  The achieved delta of every case is printed.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import adasap as OA
+from oracle import kernels as OK
+from paper_2505_13723_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+KINDS = {"rbf": OK.RBF, "matern32": OK.MATERN32}
+
+
+def _kmat(A, B, kind, ell):
+    """k(A, B) in float64 on the CPU (torch threads); squared distances by the norm
+    expansion, which is ample for measuring a difference of iterates."""
+    r2 = (A * A).sum(1)[:, None] + (B * B).sum(1)[None, :] - 2.0 * (A @ B.T)
+    r2.clamp_(min=0.0)
+    if kind == OK.RBF:
+        return torch.exp(r2 * (-0.5 / (ell * ell)))
+    a = torch.sqrt(r2) * (math.sqrt(3.0) / ell)
+    return (1.0 + a) * torch.exp(-a)
+
+
+def _klam_norm2(Xrows, XS, E, Erows, kind, ell, lam, chunk=2048):
+    """sum over the given rows of |(K E)_i + lambda E_i|^2, with E supported on XS's rows."""
+    tot = 0.0
+    for i0 in range(0, Xrows.shape[0], chunk):
+        R = _kmat(Xrows[i0:i0 + chunk], XS, kind, ell) @ E
+        if Erows is not None:
+            R += lam * Erows[i0:i0 + chunk]
+        tot += float((R * R).sum())
+    return tot
+
+
+def _delta_support(X, Y, S, E_S, kind, ell, lam, m_out, seed):
+    """delta for an iterate difference supported on the ascending rows S: exact over S,
+    plus an unbiased estimate over the other rows from m_out uniform samples."""
+    Xt = torch.as_tensor(X, dtype=torch.float64)
+    XS = Xt[torch.as_tensor(S)]
+    E = torch.as_tensor(E_S, dtype=torch.float64)
+    num = _klam_norm2(XS, XS, E, E, kind, ell, lam)
+    n = X.shape[0]
+    rest = n - S.size
+    if rest > 0 and m_out > 0:
+        mask = np.ones(n, dtype=bool)
+        mask[S] = False
+        others = np.flatnonzero(mask)
+        pick = np.random.default_rng(seed).choice(others, min(m_out, rest), replace=False)
+        num += _klam_norm2(Xt[torch.as_tensor(pick)], XS, E, None, kind, ell, lam) * rest / pick.size
+    return math.sqrt(num) / float(np.linalg.norm(Y))
+
+
+def _solve(lib, X, Y, precision, T, seed, **kw):
+    cfg = lib.config(max_iters=T, seed=seed, precision=precision, **kw)
+    h = lib.create(cfg, X, Y)
+    W = torch.zeros_like(Y)
+    rep = h.solve(W)
+    tr = h.trace(T)
+    h.close()
+    return W, rep, tr
+
+
+# ---------------------------------------------------------------- mid-size, dense oracle
+MID = dict(n=40_000, d=11, k=20, b=4096, r=128, T=3, lam=1e-2, ell=1.5, seed=31)
+
+
+@pytest.fixture(scope="module")
+def mid_inputs():
+    X, Y = inputs.make_c3(seed=MID["seed"], n=MID["n"], d=MID["d"], k=MID["k"], ell=MID["ell"],
+                          lam=MID["lam"], device="cpu", dtype=torch.float64)
+    return X.numpy(), Y.numpy()
+
+
+_mid_cache = {}
+
+
+def _mid_oracle(X, Y, reduced):
+    if reduced not in _mid_cache:
+        Xo = X.astype(np.float32).astype(np.float64) if reduced else X
+        Yo = Y.astype(np.float32).astype(np.float64) if reduced else Y
+        print("mid-size oracle (%s inputs) ..." % ("float32" if reduced else "float64"), flush=True)
+        W, info = OA.adasap(Xo, Yo, OK.RBF, MID["ell"], MID["lam"], MID["b"], MID["r"], MID["T"],
+                            MID["seed"], eps_sketch=2.0 ** -23 if reduced else 2.0 ** -52)
+        _mid_cache[reduced] = (Xo, Yo, W, info)
+    return _mid_cache[reduced]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-3), ("mixed", 1e-3)])
+def test_midsize_trajectory_matches_dense_oracle(lib, mid_inputs, precision, tol):
+    X, Y = mid_inputs
+    reduced = precision != "fp64"
+    Xo, Yo, Wo, info = _mid_oracle(X, Y, reduced)
+    dt = torch.float32 if reduced else torch.float64
+    Xd = torch.as_tensor(Xo).to(dt).cuda()
+    Yd = torch.as_tensor(Yo).to(dt).cuda()
+    print("mid-size GPU solve %s ..." % precision, flush=True)
+    W, rep, tr = _solve(lib, Xd, Yd, precision, MID["T"], MID["seed"], kernel="rbf",
+                        lengthscale=MID["ell"], lam=MID["lam"], block_size=MID["b"], rank=MID["r"])
+    assert rep["iters"] == MID["T"]
+    Wg = W.cpu().double().numpy()
+    S = np.flatnonzero(np.any(Wo != 0, axis=1))
+    outside = np.setdiff1d(np.arange(MID["n"]), S)
+    assert not np.any(Wg[outside]), "GPU iterate nonzero outside the sampled rows"
+    eta_err = np.max(np.abs(tr["eta"] - info["eta"]) / info["eta"])
+    rho_err = np.max(np.abs(tr["rho"] - info["rho"]) / info["rho"])
+    d = _delta_support(Xo, Yo, S, Wg[S] - Wo[S], OK.RBF, MID["ell"], MID["lam"], 8192, 1)
+    print("mid-size %s: delta = %.3e, eta rel err %.2e, rho rel err %.2e"
+          % (precision, d, eta_err, rho_err), flush=True)
+    rtol = 1e-8 if precision == "fp64" else 1e-3
+    assert eta_err <= rtol and rho_err <= rtol, (eta_err, rho_err)
+    assert d <= tol, d
+
+
+# ---------------------------------------------------------------- full size, support oracle
+def _fullsize(lib, name, kname, precision, m_out):
+    w = inputs.WORKLOADS[name]
+    kind = KINDS[kname]
+    T = 2
+    print("generating %s ..." % name, flush=True)
+    if name.startswith("c3"):
+        X, Y = inputs.make_c3(seed=w["seed"], n=w["n"], d=w["d"], k=w["k"], ell=w["ell"],
+                              lam=w["lam"], device="cuda")
+    else:
+        X, y = inputs.make_c2(seed=w["seed"], n=w["n"], d=w["d"], ell=w["ell"], lam=w["lam"],
+                              device="cuda")
+        Y = y[:, None].contiguous()
+    W, rep, tr = _solve(lib, X, Y, precision, T, w["seed"], kernel=kname, lengthscale=w["ell"],
+                        lam=w["lam"], block_size=w["b"], rank=w["r"])
+    torch.cuda.synchronize()
+    print("GPU: %d iterations, eta %s, rho %s" % (rep["iters"], tr["eta"], tr["rho"]), flush=True)
+    Xh = X.double().cpu().numpy()
+    Yh = Y.double().cpu().numpy()
+    Wg = W.cpu().double().numpy()
+    del X, Y, W
+    S, WS, info = OA.adasap_from_zero(Xh, Yh, kind, w["ell"], w["lam"], w["b"], w["r"], T,
+                                      w["seed"], eps_sketch=2.0 ** -23,
+                                      log=lambda m: print(m, flush=True))
+    outside = np.ones(Xh.shape[0], dtype=bool)
+    outside[S] = False
+    assert not np.any(Wg[outside]), "GPU iterate nonzero outside the sampled rows"
+    eta_err = np.max(np.abs(tr["eta"] - info["eta"]) / info["eta"])
+    rho_err = np.max(np.abs(tr["rho"] - info["rho"]) / info["rho"])
+    werr = np.linalg.norm(Wg[S] - WS) / np.linalg.norm(WS)
+    d = _delta_support(Xh, Yh, S, Wg[S] - WS, kind, w["ell"], w["lam"], m_out, 2)
+    print("%s: delta = %.3e, |W_gpu - W_oracle| / |W_oracle| = %.3e on %d rows, eta rel err %.2e, "
+          "rho rel err %.2e" % (name, d, werr, S.size, eta_err, rho_err), flush=True)
+    assert eta_err <= 1e-3 and rho_err <= 1e-3, (eta_err, rho_err)
+    assert d <= 1e-3, d
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_fullsize_rbf_n2m_k64_mixed_two_iterations(lib):
+    _fullsize(lib, "c3_rbf_n2m_k64", "rbf", "mixed", 4096)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_fullsize_matern32_n1m_fp32_two_iterations(lib):
+    _fullsize(lib, "c2_matern32_n1m", "matern32", "fp32", 4096)

@@ -7,6 +7,8 @@ float64 paths 1e-10 relative (steps) and relative residual difference
 ||(K + lambda I)(W_gpu - W_oracle)|| / ||Y|| <= 1e-6 (solves); float32 paths 1e-5 (steps)
 and 1e-3 (solves).
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -260,3 +262,103 @@ def test_solve_after_early_exit_matches_fresh_handle(lib, precision):
     assert 0 < rep1["iters"] < 40, rep1["iters"]  # stopped early, the next head queued
     assert rep2["iters"] == rep1["iters"]
     assert torch.equal(W1, W2) and torch.equal(W1, W3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_continued_equals_one_long_solve(lib, precision):
+    # a solve of T1 iterations continued by T2 (adasap_solve_more) is the solve of T1 + T2
+    # iterations: same random streams, same Nesterov state, bit for bit
+    X, Y = inputs.make_small(71, 900, 4, 3)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Xd, Yd = dev(X, dt), dev(Y, dt)
+    kw = dict(kernel="rbf", lengthscale=1.0, lam=0.05, block_size=128, rank=32, seed=8,
+              precision=precision)
+    h = lib.create(lib.config(max_iters=12, **kw), Xd, Yd)
+    W1 = torch.zeros_like(Yd)
+    h.solve(W1)
+    h.close()
+    g = lib.create(lib.config(max_iters=5, **kw), Xd, Yd)
+    W2 = torch.zeros_like(Yd)
+    g.solve(W2)
+    rep = g.solve_more(W2, 4)
+    assert rep["iters"] == 4
+    rep = g.solve_more(W2, 3)
+    eta = g.trace(3)["eta"]
+    g.close()
+    assert torch.equal(W1, W2)
+    tr = _gpu_solve(lib, X, Y, dtype=dt, max_iters=12, **kw)[2]
+    assert np.array_equal(eta, tr["eta"][9:12])
+
+
+def test_not_converged_status_and_continuation_rules(lib):
+    from paper_2505_13723_amd.binding import AdasapError
+    X, Y = inputs.make_small(72, 500, 3, 1)
+    Xd, Yd = dev(X), dev(Y)
+    h = lib.create(lib.config(kernel="rbf", lengthscale=1.0, lam=0.05, block_size=100, rank=20,
+                              seed=2, precision="fp64", max_iters=3, tol=1e-12), Xd, Yd)
+    W = torch.zeros_like(Yd)
+    rep = h.solve(W)
+    assert rep["status"] == 7 and 0 < rep["relres"] < 1 and rep["iters"] == 3
+    assert lib.cdll.adasap_solve(h.h, ctypes.c_void_p(W.data_ptr()), None) == 7
+    with pytest.raises(AdasapError):
+        h.solve_more(W, 0)
+    h.close()
+    # refinement sweeps leave nothing to continue
+    g = lib.create(lib.config(kernel="rbf", lengthscale=1.0, lam=0.05, block_size=100, rank=20,
+                              seed=2, precision="fp64", max_iters=3, refine_sweeps=1), Xd, Yd)
+    g.solve(W)
+    with pytest.raises(AdasapError) as e:
+        g.solve_more(W, 2)
+    assert e.value.status == 1
+    g.close()
+
+
+ARD_ELL = [0.6, 1.3, 2.2, 0.9]
+
+
+@pytest.mark.parametrize("kind", ["rbf", "matern32"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32", 1e-3), ("mixed", 1e-3)])
+def test_solve_per_dimension_lengthscales_and_outputscale(lib, kind, precision, tol):
+    # the kernel of the paper's regression experiments: one lengthscale per coordinate and an
+    # output scale (appendix, hyperparameters); trajectory parity with the oracle
+    n, d, k, lam, s, b, r, T = 700, 4, 2, 0.04, 2.3, 140, 30, 15
+    X, Y = inputs.make_small(81, n, d, k)
+    reduced = precision != "fp64"
+    if reduced:
+        X, Y = X.astype(np.float32).astype(np.float64), Y.astype(np.float32).astype(np.float64)
+    ell = np.array(ARD_ELL)
+    Wo, info = OA.adasap(X, Y, KINDS[kind], ell, lam, b, r, T, 6, outputscale=s,
+                         eps_sketch=2.0 ** -23 if reduced else 2.0 ** -52)
+    Wg, rep, tr, h = _gpu_solve(lib, X, Y, dtype=torch.float32 if reduced else torch.float64,
+                                kernel=kind, lengthscales=ARD_ELL, outputscale=s, lam=lam,
+                                block_size=b, rank=r, max_iters=T, seed=6, precision=precision)
+    E = Wg - Wo
+    delta = np.linalg.norm(OK.kernel_matmul(X, X, E, KINDS[kind], ell, outputscale=s) + lam * E) / \
+        np.linalg.norm(Y)
+    assert delta <= tol, delta
+    assert np.allclose(tr["eta"], info["eta"], rtol=1e-8 if not reduced else 1e-3)
+    assert np.allclose(tr["rho"], info["rho"], rtol=1e-8 if not reduced else 1e-3)
+    # residual and prediction of the same handle
+    dt = torch.float32 if reduced else torch.float64
+    rr, _ = h.residual(dev(Wg, dt))
+    ro = OL.relres(X, Y, Wg, KINDS[kind], ell, lam, outputscale=s)[0]
+    assert rr == pytest.approx(ro, rel=1e-9 if not reduced else 1e-3)
+    Xs = np.random.default_rng(9).standard_normal((55, d))
+    if reduced:
+        Xs = Xs.astype(np.float32).astype(np.float64)
+    got = h.predict(dev(Wg, dt), dev(Xs, dt)).cpu().double().numpy()
+    ref = OL.predict(Xs, X, Wg, KINDS[kind], ell, outputscale=s)
+    bound = (1e-11 if not reduced else 2e-5) * (OK.kernel_matrix(Xs, X, KINDS[kind], ell, outputscale=s)
+                                                @ np.abs(Wg)) + 1e-9
+    assert np.all(np.abs(got - ref) <= bound)
+    h.close()
+
+
+def test_bad_lengthscales_are_rejected(lib):
+    from paper_2505_13723_amd.binding import AdasapError
+    X, Y = inputs.make_small(82, 100, 3, 1)
+    for kw in (dict(lengthscales=[1.0, 0.0, 1.0]), dict(lengthscales=[1.0, 2.0]),
+               dict(outputscale=0.0), dict(lengthscales=[1.0, float("nan"), 1.0])):
+        with pytest.raises(AdasapError) as e:
+            lib.create(lib.config(block_size=50, rank=10, precision="fp64", **kw), dev(X), dev(Y))
+        assert e.value.status == 1

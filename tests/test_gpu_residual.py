@@ -40,3 +40,68 @@ def test_residual_rows_matches_oracle(lib, precision, dtype, tol, m):
     if m == n:
         assert est == pytest.approx(h.residual(Wd)[0], rel=1e-9)
     h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_float64_certificate_rows_match_oracle(lib, precision):
+    # the float64 certificate of a float32 handle: float64 kernel values of the handle's
+    # (float32) coordinates, so it equals the oracle on those coordinates to rounding
+    n, d, k, lam, ell, m = 3000, 6, 4, 0.02, 0.9, 700
+    X, Y = inputs.make_small(62, n, d, k)
+    W = np.random.default_rng(4).standard_normal((n, k))
+    X, Y, W = (a.astype(np.float32).astype(np.float64) for a in (X, Y, W))
+    Xd, Yd, Wd = (torch.as_tensor(a, dtype=torch.float32).cuda() for a in (X, Y, W))
+    h = lib.create(lib.config(kernel="matern32", lengthscale=ell, lam=lam, block_size=200, rank=20,
+                              precision=precision), Xd, Yd)
+    est, worst, se = h.residual_rows_f64(Wd, m, 21)
+    rows = OR.sample_block(21, 0, n, m, purpose=OR.PURPOSE_RESROWS)
+    R = OL.residual_rows(X, Y, W, OK.MATERN32, ell, lam, rows)
+    a, c = (R ** 2).sum(axis=1), (Y[rows] ** 2).sum(axis=1)
+    ref = np.sqrt(a.sum() / c.sum())
+    assert est == pytest.approx(ref, rel=1e-10)
+    assert worst == pytest.approx(np.max(np.sqrt((R ** 2).sum(axis=0) / (Y[rows] ** 2).sum(axis=0))),
+                                  rel=1e-10)
+    # the delta-method standard error of the ratio estimate, written out
+    Rh = a.sum() / c.sum()
+    s2 = np.sum((a - Rh * c) ** 2) / (m - 1)
+    var = (1 - m / n) * s2 / (m * c.mean() ** 2)
+    assert se == pytest.approx(0.5 * np.sqrt(var) / Rh, rel=1e-8)
+    # at m = n the estimate is the full residual, with no sampling error
+    est_n, _, se_n = h.residual_rows_f64(Wd, n, 3)
+    assert est_n == pytest.approx(OL.relres(X, Y, W, OK.MATERN32, ell, lam)[0], rel=1e-10)
+    assert se_n == 0.0
+    h.close()
+
+
+@pytest.mark.timeout(300)
+def test_reduced_certificate_agrees_with_float64_at_n262144(lib):
+    # the hi/lo certificate a MIXED solve stops on, against float64 kernel values on the same
+    # rows, at a stop point of a solve on 2^18 points of the 11-dimensional RBF workload.
+    # Bound: each hi/lo residual entry is within 2e-5 ((K + lambda I)|W|)_ic of the exact one
+    # (the error model of the hi/lo products), so the two estimates differ by at most
+    # 2e-5 |(K + lambda I)|W||_S / |Y_S| (triangle inequality on the same rows S)
+    n, d, k, lam, ell, b, r = 1 << 18, 11, 16, 1e-2, 0.5, 4096, 128
+    X, Y = inputs.make_c3(seed=7, n=n, d=d, k=k, ell=ell, lam=lam, device="cuda")
+    cfg = lib.config(kernel="rbf", lengthscale=ell, lam=lam, block_size=b, rank=r,
+                     max_iters=4 * (n // b), seed=7, precision="mixed")
+    h = lib.create(cfg, X, Y)
+    W = torch.zeros_like(Y)
+    h.solve(W)
+    full, _ = h.residual(W)
+    m = 1 << 14
+    est16, _, rows = h.residual_rows(W, m, 5, rows=True)
+    est64, _, se = h.residual_rows_f64(W, m, 5)
+    h.close()
+    Z0 = torch.zeros_like(Y)
+    h0 = lib.create(cfg, X, Z0)
+    absw, _ = h0.residual_rows(W.abs(), m, 5)   # |(K + lambda I)|W||_S (Y = 0)
+    h0.close()
+    ys = float(torch.linalg.norm(Y[rows].double()))
+    bound = 2e-5 * absw / ys
+    print("n=2^18 MIXED after 4 passes: full hi/lo relres %.4e; rows hi/lo %.4e, float64 %.4e "
+          "(rel. s.e. %.2e); |difference| %.2e, bound %.2e"
+          % (full, est16, est64, se, abs(est16 - est64), bound), flush=True)
+    assert 1e-4 < est64 < 0.5
+    assert abs(est16 - est64) <= bound + 1e-12, (est16, est64, bound)
+    # the full residual agrees with its row estimate within a few standard errors
+    assert abs(full - est64) <= 5 * se * est64 + bound, (full, est64, se)

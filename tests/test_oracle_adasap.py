@@ -169,10 +169,10 @@ def test_planted_transposed_kernel_block_is_caught(monkeypatch):
     # evaluating the gradient with the block's rows and columns swapped breaks convergence
     orig = K.kernel_matmul
 
-    def bad(X1, X2, R, kind, ell, col_chunk=4096):
+    def bad(X1, X2, R, kind, ell, col_chunk=4096, outputscale=1.0):
         if X1.shape[0] != X2.shape[0]:
-            return orig(X1, X2, R, kind, ell) * 1.01
-        return orig(X1, X2, R, kind, ell)
+            return orig(X1, X2, R, kind, ell, outputscale=outputscale) * 1.01
+        return orig(X1, X2, R, kind, ell, outputscale=outputscale)
     monkeypatch.setattr(K, "kernel_matmul", bad)
     X, Y, kind, ell, lam = _problem(n=200, d=3, k=1, lam=0.05)
     W, _ = A.adasap(X, Y, kind, ell, lam, b=50, r=20, iters=150, seed=5)
@@ -192,3 +192,79 @@ def test_residual_rows_pins():
     Ws = OL.direct_solve(X, Y, OK.RBF, 0.7, 0.1)
     r = OL.residual_rows(X, Y, Ws, OK.RBF, 0.7, 0.1, rows)
     assert np.max(np.abs(r)) < 1e-9 * np.max(np.abs(Y))
+
+
+@pytest.mark.parametrize("kind,k", [(K.RBF, 1), (K.MATERN32, 3)])
+def test_from_zero_support_form_matches_dense_oracle(kind, k):
+    # from W0 = 0 the iterates vanish outside the sampled rows, so evaluating Step I on the
+    # touched columns only is an exact reduction: W, eta and rho agree with the dense run
+    X, Y, _, ell, lam = _problem(n=600, d=3, k=k, lam=0.02, kind=kind)
+    Wd, infod = A.adasap(X, Y, kind, ell, lam, b=90, r=25, iters=5, seed=12)
+    S, WS, infos = A.adasap_from_zero(X, Y, kind, ell, lam, b=90, r=25, iters=5, seed=12)
+    assert S.size < 600 and np.all(np.diff(S) > 0)
+    outside = np.setdiff1d(np.arange(600), S)
+    assert np.array_equal(Wd[outside], np.zeros((outside.size, k)))
+    assert np.allclose(WS, Wd[S], rtol=1e-12, atol=1e-12 * np.abs(Wd).max())
+    assert np.allclose(infos["eta"], infod["eta"], rtol=1e-12)
+    assert np.allclose(infos["rho"], infod["rho"], rtol=1e-12)
+
+
+def _accel_problem():
+    # full block (b = n) with P = I: the iteration is gradient descent on the quadratic of
+    # K + lambda I, and with mu = 1/kappa, nu = 1 the Nesterov constants of Alg. 2 are those of
+    # Nesterov's method for that quadratic, whose error contracts like (1 - kappa^-1/2)^t
+    # against (1 - 1/kappa)^t without acceleration
+    X, Y, kind, ell, lam = _problem(n=200, d=2, k=1, lam=1e-3, seed=0)
+    Kl = K.kernel_matrix(X, X, kind, ell) + lam * np.eye(200)
+    ev = np.linalg.eigvalsh(Kl)
+    Wstar = linsys.direct_solve(X, Y, kind, ell, lam)
+    err = lambda W: float(np.sqrt(np.sum((W - Wstar) * (Kl @ (W - Wstar))) /
+                                  np.sum(Wstar * (Kl @ Wstar))))
+    return X, Y, kind, ell, lam, ev[-1] / ev[0], err
+
+
+def _accel_runs(T=400):
+    X, Y, kind, ell, lam, kappa, err = _accel_problem()
+    Wa, _ = A.adasap(X, Y, kind, ell, lam, 200, 1, T, 3, precond="identity", mu=1.0 / kappa,
+                     nu=1.0)
+    Wp, _ = A.adasap(X, Y, kind, ell, lam, 200, 1, T, 3, precond="identity", accel=False)
+    return kappa, err(Wa), err(Wp)
+
+
+@pytest.mark.slow
+def test_acceleration_accelerates():
+    kappa, acc, plain = _accel_runs()
+    assert 3e4 < kappa < 3e5
+    # measured: 0.56 with acceleration, 0.99 without, after 400 iterations (kappa = 7.8e4)
+    assert acc < 0.7 and plain > 0.95, (acc, plain)
+
+
+@pytest.mark.slow
+def test_planted_momentum_slip_is_caught(monkeypatch):
+    # swapping beta and 1 - beta in the momentum constants must fail the pin above
+    orig = A.nesterov_constants
+
+    def bad(mu, nu):
+        beta, gamma, alpha = orig(mu, nu)
+        return 1.0 - beta, gamma, alpha
+    monkeypatch.setattr(A, "nesterov_constants", bad)
+    _kappa, acc, _plain = _accel_runs()
+    assert acc > 0.9, acc
+
+
+def test_outputscale_is_a_rescaled_system():
+    # (s K + lam I) W = Y is s (K + (lam/s) I) W = Y: every step of the iteration scales
+    # consistently (G, the sketch, the shift, rho and P by s; D and eta unchanged), so the run
+    # with output scale s equals the unit-scale run on Y / s with lambda / s (same mu)
+    X, Y, kind, _, lam = _problem(n=300, d=3, k=2, lam=0.03)
+    ell = np.array([0.7, 1.4, 1.0])
+    s = 3.5
+    W1, i1 = A.adasap(X, Y, kind, ell, lam, b=60, r=20, iters=8, seed=4, outputscale=s)
+    W2, i2 = A.adasap(X, Y / s, kind, ell, lam / s, b=60, r=20, iters=8, seed=4, mu=lam)
+    assert np.allclose(W1, W2, rtol=1e-10, atol=1e-12 * np.abs(W2).max())
+    assert np.allclose(i1["eta"], i2["eta"], rtol=1e-10)
+    assert np.allclose(i1["rho"], s * i2["rho"], rtol=1e-10)
+    Wd = linsys.direct_solve(X, Y, kind, ell, lam, outputscale=s)
+    assert linsys.relres(X, Y, Wd, kind, ell, lam, outputscale=s)[0] < 1e-12
+    Wl, _ = A.adasap(X, Y, kind, ell, lam, b=150, r=60, iters=600, seed=5, outputscale=s)
+    assert np.linalg.norm(Wl - Wd) <= 1e-7 * np.linalg.norm(Wd)

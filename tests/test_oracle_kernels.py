@@ -62,3 +62,21 @@ def test_kernel_matmul_chunked(pts):
     assert np.allclose(K.kernel_matmul(A, B, R, K.MATERN32, 0.9, col_chunk=5), full, rtol=1e-13)
     assert np.allclose(K.kernel_matmul(A, B, R[:, 0], K.MATERN32, 0.9, col_chunk=7), full[:, 0],
                        rtol=1e-13)
+
+
+@pytest.mark.parametrize("kind,nu", [(K.RBF, None), (K.MATERN12, 0.5), (K.MATERN32, 1.5),
+                                     (K.MATERN52, 2.5)])
+def test_per_dimension_lengthscales_and_outputscale_match_sklearn(pts, kind, nu):
+    from sklearn.gaussian_process.kernels import ConstantKernel
+    A, B = pts
+    ell = np.array([0.4, 1.7, 0.9, 3.0, 1.1])
+    sk = SkRBF(length_scale=ell) if kind == K.RBF else SkMatern(length_scale=ell, nu=nu)
+    assert np.allclose(K.kernel_matrix(A, B, kind, ell), sk(A, B), rtol=1e-12, atol=1e-300)
+    scaled = ConstantKernel(2.7, constant_value_bounds="fixed") * sk
+    assert np.allclose(K.kernel_matrix(A, B, kind, ell, outputscale=2.7), scaled(A, B),
+                       rtol=1e-12, atol=1e-300)
+    # equal per-dimension lengthscales reduce to the scalar form
+    assert np.array_equal(K.sqdist(A, B, np.full(5, 1.0)), K.sqdist(A, B))
+    R = np.random.default_rng(3).standard_normal((23, 2))
+    assert np.allclose(K.kernel_matmul(A, B, R, kind, ell, col_chunk=4, outputscale=2.7),
+                       scaled(A, B) @ R, rtol=1e-12)
