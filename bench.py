@@ -45,6 +45,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -77,8 +79,13 @@ def main():
                     help="time-to-residual runs: mixed (the headline), fp32, mixed_refine")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=384, help="oracle block rows per host core")
-    ap.add_argument("--workload", choices=["c3", "batched", "warm", "step1", "matern32_n1m", "rbf_n100m"],
-                    default="c3")
+    ap.add_argument("--workload", choices=["c3", "batched", "warm", "step1", "matern32_n1m", "rbf_n100m",
+                                           "bo"], default="c3")
+    ap.add_argument("--bo-n0", type=int, default=250_000, help="initial points of the BO workload")
+    ap.add_argument("--bo-steps", type=int, default=10)
+    ap.add_argument("--bo-acq", type=int, default=1000, help="acquisitions per BO step")
+    ap.add_argument("--bo-seeds", type=int, default=1, help="objective functions per lengthscale")
+    ap.add_argument("--bo-passes", type=int, default=10, help="ADASAP data passes per solve")
     ap.add_argument("--shape", choices=["rbf_n2m_k64", "rbf_n100m"], default="rbf_n2m_k64",
                     help="problem of the step1 workload")
     ap.add_argument("--ws-lam", type=float, default=1.0, help="noise variance of the warm workload")
@@ -100,6 +107,8 @@ def main():
         return bench_step1(args, torch, binding, inputs)
     if args.workload in ("matern32_n1m", "rbf_n100m"):
         return bench_single_k1(args, torch, binding, inputs)
+    if args.workload == "bo":
+        return bench_bo(args, torch, binding)
     cfgw = dict(inputs.WORKLOADS["c3_rbf_n2m_k64"])
     n, d, k = args.n, cfgw["d"], cfgw["k"]
     b, r, lam, ell = cfgw["b"], cfgw["r"], cfgw["lam"], cfgw["ell"]
@@ -107,7 +116,9 @@ def main():
         b = max(256, n // 122)
     lib = binding.load()
     log("generating inputs n=%d d=%d k=%d on the GPU" % (n, d, k))
-    X, Y = inputs.make_c3(seed=cfgw["seed"], n=n, d=d, k=k, ell=ell, lam=lam, device="cuda")
+    X, Y, Xt, yt, Pt = inputs.make_c3(seed=cfgw["seed"], n=n, d=d, k=k, ell=ell, lam=lam,
+                                      device="cuda", n_test=N_TEST)
+    test = (Xt, yt, Pt)
     torch.cuda.synchronize()
 
     def make(max_iters, tol=0.0, check_every=0, refine=0):
@@ -148,7 +159,7 @@ def main():
             prec, refine = {"mixed": ("mixed", 0), "fp32": ("fp32", 0),
                             "mixed_refine": ("mixed", 1)}[row]
             ttr_rows[row] = time_to_residual(torch, lib, X, Y, W, cfgw, b, n, per_pass,
-                                             args.ttr_passes, prec, refine)
+                                             args.ttr_passes, prec, refine, test)
             log("time-to-residual %s: %s" % (row, json.dumps(ttr_rows[row])))
         ttr = ttr_rows.get("mixed")
 
@@ -185,9 +196,10 @@ def main():
 
 
 CERT_ROWS = 1 << 17
+N_TEST = 16384
 
 
-def time_to_residual(torch, lib, X, Y, W, cfgw, b, n, per_pass, passes, precision, refine):
+def time_to_residual(torch, lib, X, Y, W, cfgw, b, n, per_pass, passes, precision, refine, test=None):
     """Solve from zero until the relative residual is certified <= 1e-3 in float64.
 
     The solve checks once per data pass with the row-subsampled estimate (2^17 rows, the
@@ -219,6 +231,17 @@ def time_to_residual(torch, lib, X, Y, W, cfgw, b, n, per_pass, passes, precisio
     full, full_max = h.residual(W)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    pred = None
+    if test is not None:
+        # pathwise posterior samples at the held-out points (column 0 of W solves for y, the
+        # others for prior functions plus noise) and the test RMSE / mean NLL (Sec. 5.1)
+        Xt, yt, Pt = test
+        t1 = time.perf_counter()
+        smp = h.posterior_samples(W, Xt, Pt)
+        rmse, nll = lib.predictive_metrics(smp, yt, cfgw["lam"])
+        pred = {"test_points": int(Xt.shape[0]), "samples": int(Y.shape[1] - 1),
+                "test_rmse": rmse, "test_mean_nll": nll,
+                "seconds": round(time.perf_counter() - t1, 4)}
     h.close()
     ok = est <= 1e-3
     return {"seconds": round(solve_s, 3) if ok else None, "reached": bool(ok),
@@ -227,7 +250,7 @@ def time_to_residual(torch, lib, X, Y, W, cfgw, b, n, per_pass, passes, precisio
             "relres_f64_rows": est, "relres_f64_rows_rel_se": se, "relres_f64_rows_maxcol": worst,
             "certificate_rows": CERT_ROWS, "relres_hilo_full": full, "relres_hilo_full_maxcol": full_max,
             "passes_added_after_certificate": extra, "check_every_iters": per_pass,
-            "check": "row estimate on %d rows once per pass" % CERT_ROWS}
+            "check": "row estimate on %d rows once per pass" % CERT_ROWS, "predictive": pred}
 
 
 def bench_batched(args, torch, binding, inputs):
@@ -291,6 +314,39 @@ def bench_batched(args, torch, binding, inputs):
                      "kernel_ms": round(kern_ms, 4), "algorithmic_exp_per_launch": pairs},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_bo(args, torch, binding):
+    """Parallel Thompson sampling on Matern-3/2 objectives over [0, 1]^8 (lengthscales 2 and 3,
+    noise 1e-6, b = n/5), against random search with as many evaluations."""
+    from paper_2505_13723_amd import bo
+
+    lib = binding.load()
+    res = {}
+    t0 = time.perf_counter()
+    for ell in (2.0, 3.0):
+        runs = []
+        for sd in range(args.bo_seeds):
+            out = bo.thompson_bo(lib, d=8, ell=ell, noise=1e-6, n0=args.bo_n0, steps=args.bo_steps,
+                                 acq=args.bo_acq, passes=args.bo_passes, seed=100 * sd + int(ell),
+                                 log=log)
+            log("BO ell=%.1f seed %d: improvement %.3f%%" % (ell, sd, out["improvement_percent"]))
+            runs.append(out)
+        res["ell_%.1f" % ell] = {
+            "improvement_percent_mean": float(np.mean([r["improvement_percent"] for r in runs])),
+            "runs": [{k: v for k, v in r.items()} for r in runs]}
+    wall = time.perf_counter() - t0
+    line = {"metric": "BO improvement over random search (%), Matern-3/2 on [0,1]^8, 1 GPU",
+            "value": round(float(np.mean([v["improvement_percent_mean"] for v in res.values()])), 4),
+            "unit": "%", "n_gpus": 1, "steps": args.bo_steps, "warmup": 0, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f16 matrix-core products (MIXED)",
+            "data": "synthetic (random-feature Matern-3/2 objectives)",
+            "config": {"workload": "bo_matern32_d8_n%d" % args.bo_n0, "n0": args.bo_n0,
+                       "acquisitions_per_step": args.bo_acq, "steps": args.bo_steps,
+                       "objectives_per_lengthscale": args.bo_seeds, "passes_per_solve": args.bo_passes,
+                       "b": "n/5", "noise": 1e-6},
+            "results": res, "wall_seconds": round(wall, 2), "roofline": None, "cpu_baseline": None}
     print(json.dumps(line), flush=True)
 
 

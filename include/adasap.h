@@ -64,8 +64,15 @@ typedef enum { ADASAP_RBF = 0, ADASAP_MATERN12 = 1, ADASAP_MATERN32 = 2, ADASAP_
 typedef enum { ADASAP_FP64 = 0, ADASAP_FP32 = 1, ADASAP_MIXED = 2 } adasap_precision_t;
 
 /* Preconditioner of the block step.  NYSTROM is ADASAP (P_B = U S U^T + rho I);
- * IDENTITY is ADASAP-I (Sec. 5, P_B = I, step size from powering on K_BB + lambda I). */
-typedef enum { ADASAP_PRECOND_NYSTROM = 0, ADASAP_PRECOND_IDENTITY = 1 } adasap_precond_t;
+ * IDENTITY is ADASAP-I (Sec. 5, P_B = I, step size from powering on K_BB + lambda I);
+ * EXACT is the exact block projection of SAP (Sec. 3, Alg. 1): P_B = K_BB + lambda I, formed
+ * and Cholesky-factored in float64 (b <= 16384, b x b float64 of workspace), step size 1 (the
+ * preconditioned block operator is the identity); with accel = 0 this is Alg. 1 itself, with
+ * accel = 1 the Nesterov step of Alg. 2 around it.  EXACT takes FP64 or FP32 precision: the
+ * unit step amplifies the float16 error of MIXED block gradients by up to 1/lambda, so MIXED
+ * is rejected (ADASAP_ERR_INVALID_ARG). */
+typedef enum { ADASAP_PRECOND_NYSTROM = 0, ADASAP_PRECOND_IDENTITY = 1,
+               ADASAP_PRECOND_EXACT = 2 } adasap_precond_t;
 
 /* Element type of X, Y, W, Xstar and prediction outputs. */
 typedef enum { ADASAP_DTYPE_F32 = 0, ADASAP_DTYPE_F64 = 1 } adasap_dtype_t;
@@ -166,6 +173,37 @@ adasap_status_t adasap_solve_more(adasap_handle_t h, void* W, int64_t iters,
  * W (device, n x k), Xstar (device, m x d), out (device, m x k), all handle dtype. */
 adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, const void* Xstar,
                                void* out);
+
+/* Pathwise posterior samples (Sec. 2.1, pathwise conditioning): a posterior sample at X* is
+ * f(X*) + k(X*, X)(K + lambda I)^{-1}(y - f(X) - zeta) for a prior function f and
+ * zeta ~ N(0, lambda I).  W (device, n x k, handle dtype) must solve the handle's systems for
+ * the right-hand sides Y = [y | f_1(X) + zeta_1 | ... | f_{k-1}(X) + zeta_{k-1}] (column 0
+ * the observations, column s a prior function plus noise); prior_star (device, m x (k - 1),
+ * handle dtype, may be NULL when k = 1) holds f_s(X*).  out (device, m x k, handle dtype)
+ * receives the posterior mean k(X*, X) W_0 in column 0 and sample s,
+ * f_s(X*) + k(X*, X)(W_0 - W_s), in column s; the products run as in adasap_predict.
+ * Synchronises the stream. */
+adasap_status_t adasap_posterior_samples(adasap_handle_t h, const void* W, int64_t m,
+                                         const void* Xstar, const void* prior_star, void* out);
+
+/* Predictive metrics on held-out data (Sec. 5.1: test RMSE and mean negative log-likelihood
+ * from pathwise samples).  samples (device, m x k, dtype): posterior mean in column 0 and
+ * k - 1 samples, as written by adasap_posterior_samples; ystar (device, m, dtype): the
+ * held-out targets.  rmse = sqrt(mean_i (mu_i - y*_i)^2); nll = mean_i of the negative log
+ * density of y*_i under N(mu_i, v_i + lambda), v_i the mean squared deviation of the samples
+ * from mu_i (v_i = 0 when k = 1).  float64 accumulation, fixed order; host outputs, may be
+ * NULL.  Synchronises the stream. */
+adasap_status_t adasap_predictive_metrics(int64_t m, int32_t k, const void* samples,
+                                          const void* ystar, double lambda, int32_t dtype,
+                                          void* stream, double* rmse, double* nll);
+
+/* Acquisition step of parallel Thompson sampling (Sec. 5.3 Bayesian optimisation: each
+ * acquired point maximises one posterior sample over candidate points): for each of the k
+ * columns of a (device, m x k with row stride ld >= k, dtype), the index of its largest entry
+ * (the first such row on ties; NaN entries never win; -1 if a column has no comparable
+ * entry).  out: device int64[k].  Synchronises the stream. */
+adasap_status_t adasap_column_argmax(int64_t m, int32_t k, int64_t ld, const void* a,
+                                     int32_t dtype, void* stream, int64_t* out);
 
 /* Relative residual ||(K + lambda I) W - Y||_F / ||Y||_F with float64 accumulation
  * (relres) and its maximum over columns (relres_maxcol); host outputs, may be NULL. */

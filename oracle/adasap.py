@@ -2,33 +2,29 @@
 
 Test infrastructure (see the package docstring).
 
-One iteration t, in the paper's order and notation (Sec. 4.2, Alg. 2):
-
-  Step I    sample B (size b) uniformly;  G = K_{B,:} Z_t + lambda Z_t[B] - Y_B
-  Step II   Omega (b x r) Gaussian;  sketch K_BB Omega
-  Step III  U, S = NysApprox(K_BB Omega, Omega);  P_B = U S U^T + rho I with
-            rho = S_rr + lambda (the paper's rule) or a fixed rho;
-            eta_B = GetStepsize(P_B, K_BB + lambda I)
-  Step IV   D_t = P_B^{-1} G;  Nesterov update
-            W_{t+1} = Z_t - eta I_B^T D_t
-            V_{t+1} = beta V_t + (1 - beta) Z_t - gamma eta I_B^T D_t
-            Z_{t+1} = alpha V_{t+1} + (1 - alpha) W_{t+1}
-  with beta = 1 - sqrt(mu/nu), gamma = 1/sqrt(mu nu), alpha = 1/(1 + gamma nu),
-  mu = lambda and nu = n/b by default (Sec. 4.2), V_0 = Z_0 = W_0.
+Each iteration of Alg. 2 (Sec. 4) draws a uniform block B of b row indices, forms the block
+of the gradient of the quadratic (K + lambda I) W - Y at the extrapolated point, builds the
+randomized Nystrom preconditioner P_B of K_BB + rho I from a Gaussian sketch of K_BB
+(Alg. NysApprox, nystrom.py), estimates the step size as the reciprocal of the largest
+eigenvalue of P_B^{-1/2}(K_BB + lambda I)P_B^{-1/2} by randomized powering (Alg. GetStepsize,
+stepsize.py), and moves the block rows along -P_B^{-1} G.  The accelerated form keeps three
+sequences W, V, Z (Alg. NestAcc): W steps from Z, V mixes its previous value with Z and takes a
+longer step, and Z is the convex combination of V and W that the next gradient is taken at.
+The mixing weights come from mu and nu (defaults lambda and n/b, Sec. 4.2):
+beta = 1 - sqrt(mu/nu), gamma = 1/sqrt(mu nu), alpha = 1/(1 + gamma nu); V_0 = Z_0 = W_0.
 
 Readings of the printed listings (each switchable for the tests):
-  * the gradient is taken at Z_t (grad_at_z=True): the accelerated step moves
-    from Z_t, and the printed Step IV's W_t is read as Z_t;
-  * Z_{t+1} uses V_{t+1} (z_uses_v_next=True), the standard accelerated
+  * the gradient is taken at Z_t (grad_at_z=True), since the accelerated step moves from
+    Z_t (the printed listing evaluates it at W_t);
+  * Z_{t+1} mixes the updated V_{t+1} (z_uses_v_next=True), the accelerated
     sketch-and-project recurrence the constants come from;
-  * tail averaging is off unless asked for; when on, W_bar is the mean of
+  * tail averaging is off unless asked for; when on, the returned iterate is the mean of
     W_j for j = floor(T/2) .. T-1 (the form the theorems use).
 
-Modes: precond='nystrom' (ADASAP), 'identity' (ADASAP-I, Sec. 5: P_B = I,
-eta from powering on K_BB + lambda I), 'exact' (P_B = K_BB + lambda I);
-accel=False replaces the Nesterov step by W_{t+1} = W_t - eta I_B^T D_t with
-the gradient at W_t; mode 'sap' is Alg. 1 (exact block solve, eta = 1,
-no acceleration).
+Modes: precond='nystrom' (ADASAP), 'identity' (ADASAP-I, Sec. 5: P_B = I, the step size from
+powering on K_BB + lambda I), 'exact' (P_B = K_BB + lambda I); accel=False replaces the
+Nesterov step by W_{t+1} = W_t - eta I_B^T D_t with the gradient at W_t; 'sap' is Alg. 1
+(exact block solve, unit step, no acceleration).
 """
 import math
 

@@ -2,27 +2,23 @@
 
 Test infrastructure (see the package docstring).
 
-NysApprox (Appendix, Alg. NysApprox, after Tropp et al. 2017 Alg. 3) as read
-consistently (the printed listing forms the triangular solve from the
-unshifted sketch and writes S^2 for Sigma^2):
+What is computed (Alg. NysApprox, in the consistent form of Tropp et al. 2017, reading A5):
+given a PSD matrix M seen only through its sketch M Omega with a Gaussian test matrix
+Omega, the rank-r Nystrom approximation M_hat = (M Omega)(Omega^T M Omega)^+(M Omega)^T is
+returned in eigen form U diag(S) U^T.  For numerical safety the sketch is first moved to
+that of M + Delta I, with Delta a machine-epsilon multiple of tr(Omega^T M Omega) (epsilon of
+the precision the sketch was formed in: 2**-52 for float64, 2**-23 for float32); the core
+Omega^T (M + Delta I) Omega is factored by Cholesky, the shifted sketch is multiplied by the
+inverse of that factor, and the squared singular values of the result, less Delta and
+clipped at zero, are the eigenvalues S (the printed listing forms the triangular solve from
+the unshifted sketch and writes S^2 where the squared singular values are meant).  When the
+Cholesky factorisation fails, Delta grows tenfold and the step is repeated, at most 5 times
+(a case the paper does not discuss).
 
-    Delta = eps * tr(Omega^T (M Omega))          shift for stability
-    Y_nu  = M Omega + Delta * Omega              shifted sketch
-    C     = Omega^T Y_nu  (symmetrised),  C = R^T R  (upper Cholesky factor R)
-    B     = Y_nu R^{-1}                          triangular solve
-    U, Sigma, _ = thin SVD of B
-    S     = max(0, Sigma^2 - Delta)              remove the shift
-
-so that Mhat = U diag(S) U^T.  eps is the machine epsilon of the precision the
-sketch was computed in (2**-52 for a float64 sketch, 2**-23 for float32).  If
-the Cholesky factorisation fails, Delta is multiplied by 10 and the step is
-retried, at most 5 times (reading for a case the paper does not discuss).
-
-Woodbury applies with P = U S U^T + rho I (Eq. inv_nys_woodbury and
-Eq. inv_sqrt_nys_woodbury):
-
-    P^{-1}   g = U (S + rho)^{-1}   U^T g + (g - U U^T g) / rho
-    P^{-1/2} v = U (S + rho)^{-1/2} U^T v + (v - U U^T v) / sqrt(rho)
+The preconditioner P = U diag(S) U^T + rho I is inverted through the Woodbury identity
+(Eq. inv_nys_woodbury and Eq. inv_sqrt_nys_woodbury): on range(U) P acts as S + rho, on its
+orthogonal complement as rho, so P^{-1} and P^{-1/2} scale the two components by
+(S + rho)^{-1} (or ^{-1/2}) and rho^{-1} (or ^{-1/2}).
 """
 import numpy as np
 
@@ -57,7 +53,7 @@ def nystrom(Ysk, Omega, eps=EPS64, max_retries=5):
     Omega = np.asarray(Omega, dtype=np.float64)
     delta = eps * np.trace(Omega.T @ Ysk)
     for _attempt in range(max_retries + 1):
-        Ynu = Ysk + delta * Omega
+        Ynu = Ysk + delta * Omega              # sketch of M + delta I
         C = Omega.T @ Ynu
         C = 0.5 * (C + C.T)
         try:
@@ -65,8 +61,7 @@ def nystrom(Ysk, Omega, eps=EPS64, max_retries=5):
         except NotPositiveDefinite:
             delta *= 10.0
             continue
-        # B = Y_nu R^{-1}: solve B R = Y_nu row by row (R upper triangular)
-        Bm = np.linalg.solve(R.T, Ynu.T).T
+        Bm = np.linalg.solve(R.T, Ynu.T).T     # Bm R = Y_nu
         U, sigma, _ = np.linalg.svd(Bm, full_matrices=False)
         S = np.maximum(0.0, sigma * sigma - delta)
         return U, S, delta

@@ -91,6 +91,10 @@ _SIGNATURES = {
     "adasap_solve": (_I32, [_P, _P, ctypes.POINTER(Report)]),
     "adasap_solve_more": (_I32, [_P, _P, _I64, ctypes.POINTER(Report)]),
     "adasap_predict": (_I32, [_P, _P, _I64, _P, _P]),
+    "adasap_posterior_samples": (_I32, [_P, _P, _I64, _P, _P, _P]),
+    "adasap_column_argmax": (_I32, [_I64, _I32, _I64, _P, _I32, _P, _P]),
+    "adasap_predictive_metrics": (_I32, [_I64, _I32, _P, _P, _D, _I32, _P, ctypes.POINTER(_D),
+                                         ctypes.POINTER(_D)]),
     "adasap_residual": (_I32, [_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "adasap_get_trace": (_I32, [_P, _P, _P, _P, _I64]),
     "adasap_block_gradient": (_I32, [_P, _I64, _P, _P, _P]),
@@ -259,6 +263,27 @@ class Library:
                                                   _ptr(R2), _ptr(out), _dtype_code(Xr), _stream()))
         return out if R.dim() == 2 else out[:, 0]
 
+    def predictive_metrics(self, samples, ystar, lam):
+        """(test RMSE, mean NLL) of [posterior mean | samples] against ystar."""
+        _check_dev(samples, ystar)
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self.check(self.cdll.adasap_predictive_metrics(samples.shape[0], samples.shape[1],
+                                                       _ptr(samples), _ptr(ystar), float(lam),
+                                                       _dtype_code(samples), _stream(),
+                                                       ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def column_argmax(self, a):
+        """Row index of the largest entry of every column of a (m x k device matrix, any row
+        stride), as a device int64 tensor."""
+        torch = _torch()
+        if not a.is_cuda or a.dim() != 2 or a.stride(1) != 1:
+            raise ValueError("expected a device matrix with contiguous rows")
+        out = torch.empty(a.shape[1], dtype=torch.int64, device=a.device)
+        self.check(self.cdll.adasap_column_argmax(a.shape[0], a.shape[1], a.stride(0), _ptr(a),
+                                                  _dtype_code(a), _stream(), _ptr(out)))
+        return out
+
     def nystrom(self, Ysk, Omega, eps):
         torch = _torch()
         _check_dev(Ysk, Omega)
@@ -413,6 +438,15 @@ class Handle:
         out = torch.empty((Xstar.shape[0], self.Y.shape[1]), dtype=self.X.dtype, device=self.X.device)
         self.lib.check(self.lib.cdll.adasap_predict(self.h, _ptr(W), Xstar.shape[0], _ptr(Xstar),
                                                     _ptr(out)))
+        return out
+
+    def posterior_samples(self, W, Xstar, prior_star):
+        """[posterior mean | k - 1 pathwise samples] at Xstar (m x k) from the solutions W."""
+        torch = _torch()
+        _check_dev(W, Xstar, prior_star)
+        out = torch.empty((Xstar.shape[0], self.Y.shape[1]), dtype=self.X.dtype, device=self.X.device)
+        self.lib.check(self.lib.cdll.adasap_posterior_samples(self.h, _ptr(W), Xstar.shape[0],
+                                                              _ptr(Xstar), _ptr(prior_star), _ptr(out)))
         return out
 
     def residual(self, W):

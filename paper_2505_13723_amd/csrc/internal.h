@@ -118,6 +118,23 @@ adasap_status_t normalize_into(int64_t b, const double* z, double* v, IterScalar
 adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf& part,
                                   hipStream_t s, int P = 1);
 
+// ---- exact block projection (chol.hip) ------------------------------------------------------
+// H (b x b float64) = outputscale * k(X_B, X_B) + lam I from the points X[B[i]] (type xt), then
+// H = L L^T in place (lower triangle) with the inverses of the diagonal blocks in Linv
+// (exact_linv_doubles(b) doubles); sc->eta = 1, sc->rho = lam; a failed pivot sets sc->failed.
+size_t exact_linv_doubles(int64_t b);
+adasap_status_t exact_factor(int kern, double ell, double outputscale, double lam, int64_t b, int d,
+                             const void* X, DT xt, const int64_t* B, double* H, double* Linv,
+                             IterScalars* sc, hipStream_t s);
+// Y (b x k float64) <- (L L^T)^{-1} Y with the factor of exact_factor
+adasap_status_t exact_solve(int64_t b, int k, const double* H, const double* Linv, double* Y,
+                            hipStream_t s);
+
+// ---- pathwise conditioning (pathwise.hip) ----------------------------------------------------
+// out[i, s] = prior[i, s - 1] + out[i, 0] - out[i, s] for s = 1 .. k-1 (out: m x k)
+adasap_status_t pathwise_combine(int64_t m, int k, const void* prior, DT pt, void* out, DT ot,
+                                 hipStream_t s);
+
 // ---- random numbers (rng.hip) -------------------------------------------------------------
 // Batched over P problems: problem p uses seed + p and writes out + p * count.
 // If t_dev is set, the stream counter is read from device memory (*t_dev) instead of t.

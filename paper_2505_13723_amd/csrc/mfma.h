@@ -72,6 +72,26 @@ adasap_status_t mfma_product_rows(const MfmaPack& pk, const void* rowq, int64_t 
                                   DT rt, int k, int mode, void* out, DT ot, MfmaWork& w,
                                   hipStream_t s, double kscale = 1.0);
 
+// ---- fused Nesterov update and float16 packing of Z (MIXED path) ------------------------------
+// The packed float16 Z of the Step-I product is produced by the update pass itself: fused_init
+// packs the starting Z and records column maxima of |V| and |Z|; each fused_update applies the
+// Nesterov step (all rows + the rows of B with direction D and sc->eta), writes V, Z (and W
+// when non-null) and packs the new Z with scales bounded from the recorded maxima.
+struct FusedUpd {
+  DevBuf pos;      // int64[n]: (stamp << 32) | j for the rows B[j] of the current block
+  DevBuf packed;   // float16 Z in the Step-I operand order
+  DevBuf scale;    // float[k] power-of-two column scales of the packed Z
+  DevBuf part;     // per-workgroup maxima [nwg][2][k] of |V| and |Z|
+  int nwg = 0, mode = 0, nq = 0;
+  uint32_t stamp = 0;
+};
+adasap_status_t fused_init(const MfmaPack& pk, FusedUpd& f, int k, const float* V, const float* Z,
+                           MfmaWork& w, hipStream_t s);
+RhsPacked fused_rhs(const FusedUpd& f);
+adasap_status_t fused_update(const MfmaPack& pk, FusedUpd& f, int k, const int64_t* B, int64_t b,
+                             const double* D, const IterScalars* sc, const NestCoef& c, float* V,
+                             float* Z, void* W, DT wt, hipStream_t s);
+
 // ---- batches of independent problems (all with two K-steps, d <= 16) --------------------------
 // Points of problem p occupy rows row_off[p] .. row_off[p] + ntiles[p]*32 of the global row
 // space (padding rows are zero); block indices passed to the batch launchers are global rows.

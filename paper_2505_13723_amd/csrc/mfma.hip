@@ -709,7 +709,7 @@ __global__ __launch_bounds__(256, (mk_occupancy<KERN, MODE, NQ>())) void mk_kern
 // m + 32 (k / 8), element k % 8) and the row fragments from the row vectors.  The K Z products
 // are software-pipelined by one tile as in the 16x16 form; each accumulator adds the tiles
 // in order.
-template <int KS, int NS, int KERN, int NQW>
+template <int KS, int NS, int KERN, int NQW, bool DEFER>
 __device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const void* rhs_p,
                           const int64_t* ridx, int rw, int64_t T0, int64_t T1, float* out) {
   constexpr int A_FR = 2 * KS * 64, R_FR = NQW * 2 * 64, TOTAL16 = A_FR + R_FR;
@@ -807,14 +807,16 @@ __device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const
     });
   };
   auto kz_deferred = [&]() __attribute__((always_inline)) {
-    static_for<2>([&](auto rc) {
-      constexpr int rt = decltype(rc)::value;
-      static_for<NQW>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        acc[rt][q] = mfma32(Rp[q][0], Kp[rt][0], acc[rt][q]);
-        acc[rt][q] = mfma32(Rp[q][1], Kp[rt][1], acc[rt][q]);
+    if constexpr (DEFER) {
+      static_for<2>([&](auto rc) {
+        constexpr int rt = decltype(rc)::value;
+        static_for<NQW>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          acc[rt][q] = mfma32(Rp[q][0], Kp[rt][0], acc[rt][q]);
+          acc[rt][q] = mfma32(Rp[q][1], Kp[rt][1], acc[rt][q]);
+        });
       });
-    });
+    }
   };
   auto compute = [&](int buf) __attribute__((always_inline)) {
     const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
@@ -830,23 +832,88 @@ __device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const
       constexpr int sl = decltype(sc)::value;
       A[sl] = Af[aidx[sl]];
     });
-    static_for<2>([&](auto rc) {
-      constexpr int rt = decltype(rc)::value;
-      f16v D;
+    if constexpr (DEFER) {
+      static_for<2>([&](auto rc) {
+        constexpr int rt = decltype(rc)::value;
+        f16v D;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) D[r] = 0.0f;
+        for (int r = 0; r < 16; ++r) D[r] = 0.0f;
+        static_for<NS>([&](auto sc) {
+          constexpr int sl = decltype(sc)::value;
+          D = mfma32(A[sl], Bfr[rt][sl], D);
+        });
+        static_for<2>([&](auto tc) {
+          constexpr int t = decltype(tc)::value;
+          half8 Kh;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) Kh[j] = (_Float16)kval<KERN>(D[8 * t + j], a.p);
+          Kp[rt][t] = Kh;
+        });
+      });
+    } else {
+      // Interleaved within the wave: row tile 1's distance MFMAs issue beside row tile 0's
+      // exponentials and conversions, and row tile 0's K Z MFMAs beside row tile 1's, so that
+      // the matrix cores and the vector ALUs work at the same time.  Scheduling barriers keep
+      // the compiler from regrouping the chunks.
+      f16v D0, D1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        D0[r] = 0.0f;
+        D1[r] = 0.0f;
+      }
       static_for<NS>([&](auto sc) {
         constexpr int sl = decltype(sc)::value;
-        D = mfma32(A[sl], Bfr[rt][sl], D);
+        D0 = mfma32(A[sl], Bfr[0][sl], D0);
       });
-      static_for<2>([&](auto tc) {
-        constexpr int t = decltype(tc)::value;
-        half8 Kh;
+      // eight kernel values of row tile rt, slice t, half h (four values) as float16
+      auto kv4 = [&](const f16v& D, half8& K, int t, int h) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) Kh[j] = (_Float16)kval<KERN>(D[8 * t + j], a.p);
-        Kp[rt][t] = Kh;
+        for (int j = 0; j < 4; ++j) K[4 * h + j] = (_Float16)kval<KERN>(D[8 * t + 4 * h + j], a.p);
+      };
+      half8 K00, K01, K10, K11;
+      // distance of row tile 1 (NS MFMAs) beside the 16 kernel values of row tile 0
+      static_for<NS>([&](auto sc) {
+        constexpr int sl = decltype(sc)::value;
+        __builtin_amdgcn_sched_barrier(0);
+        D1 = mfma32(A[sl], Bfr[1][sl], D1);
+        // NS = 2, 3 or 4 MFMAs share the four quarter-slices of row tile 0
+        static_for<4>([&](auto qc) {
+          constexpr int qq = decltype(qc)::value;
+          if constexpr (qq * NS / 4 == sl) {
+            if constexpr (qq < 2) kv4(D0, K00, 0, qq);
+            else kv4(D0, K01, 1, qq - 2);
+          }
+        });
       });
-    });
+      __builtin_amdgcn_sched_barrier(0);
+      Kp[0][0] = K00;
+      Kp[0][1] = K01;
+      // K Z of row tile 0 (2 NQW MFMAs) beside the kernel values of row tile 1
+      static_for<NQW>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        static_for<2>([&](auto tc) {
+          constexpr int t = decltype(tc)::value;
+          constexpr int slot = 2 * q + t;  // 0 .. 2 NQW - 1
+          __builtin_amdgcn_sched_barrier(0);
+          acc[0][q] = mfma32(Rp[q][t], Kp[0][t], acc[0][q]);
+          static_for<4>([&](auto hc) {
+            constexpr int hh = decltype(hc)::value;
+            if constexpr (hh * (2 * NQW) / 4 == slot) {
+              if constexpr (hh < 2) kv4(D1, K10, 0, hh);
+              else kv4(D1, K11, 1, hh - 2);
+            }
+          });
+        });
+      });
+      __builtin_amdgcn_sched_barrier(0);
+      Kp[1][0] = K10;
+      Kp[1][1] = K11;
+      static_for<NQW>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        acc[1][q] = mfma32(Rp[q][0], Kp[1][0], acc[1][q]);
+        acc[1][q] = mfma32(Rp[q][1], Kp[1][1], acc[1][q]);
+      });
+    }
   };
 
   if (T0 < T1) {
@@ -909,7 +976,7 @@ __global__ __launch_bounds__(256, 2) void mkw_kernel(MkArgs a) {
   const int64_t T0 = (int64_t)split * a.tiles_per_split;
   int64_t T1 = T0 + a.tiles_per_split;
   if (T1 > a.ntiles) T1 = a.ntiles;
-  mkw_tiles<KS, NS, KERN, NQW>(
+  mkw_tiles<KS, NS, KERN, NQW, true>(
       a, lds, a.colA + prob * a.bs_colA, static_cast<const char*>(a.rhs) + prob * a.bs_rhs,
       a.ridx ? a.ridx + prob * a.bs_ridx : nullptr, rw, T0, T1,
       a.part + prob * a.bs_part + (int64_t)split * a.m * a.k);
@@ -1217,6 +1284,175 @@ adasap_status_t pack_rhs(const void* R, DT rt, int64_t rows, int k, int64_t ldr,
   return ADASAP_OK;
 }
 
+// ---------------------------------------------------------------- fused update and packing
+// The Nesterov update of the MIXED path (Alg. NestAcc) and the float16 packing of the next
+// iterate for Step I in one streaming pass.  Each workgroup takes tiles of 32 rows
+// (grid-stride): it applies the all-rows 2x2 map to (V, Z), the block-row correction to the
+// rows of B (found through pos: pos[i] = (stamp << 32) | j when row i is B[j] in the current
+// iteration), writes V, Z and, when asked, W, and packs the new Z tile in the operand order of
+// the Step-I product with the per-column power-of-two scales computed beforehand from a bound
+// (fused_scale_kernel).  It also records per-column maxima of |V| and |Z| for the next bound.
+constexpr int FU_TILES_MAX = 4096;  // workgroups of the fused pass (grid-stride over tiles)
+
+__global__ __launch_bounds__(256) void vzmax_partial_kernel(int64_t n, int k, int64_t ntiles,
+                                                            const float* __restrict__ V,
+                                                            const float* __restrict__ Z,
+                                                            float* __restrict__ part) {
+  __shared__ unsigned int mv[128], mz[128];
+  for (int c = threadIdx.x; c < k; c += 256) mv[c] = mz[c] = 0u;
+  __syncthreads();
+  for (int64_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
+    for (int e = threadIdx.x; e < 32 * k; e += 256) {
+      const int64_t i = T * TILE + e / k;
+      const int c = e % k;
+      if (i < n) {
+        atomicMax(&mv[c], __float_as_uint(fabsf(V[i * k + c])));
+        atomicMax(&mz[c], __float_as_uint(fabsf(Z[i * k + c])));
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += 256) {
+    part[((int64_t)blockIdx.x * 2 + 0) * k + c] = __uint_as_float(mv[c]);
+    part[((int64_t)blockIdx.x * 2 + 1) * k + c] = __uint_as_float(mz[c]);
+  }
+}
+
+__global__ void pos_scatter_kernel(int64_t b, const int64_t* __restrict__ B, uint32_t stamp,
+                                   int64_t* __restrict__ pos) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < b) pos[B[j]] = (int64_t)(((uint64_t)stamp << 32) | (uint64_t)j);
+}
+
+// scale[c]: power of two with bound_c / scale <= 2^14, bound_c = max(|V|, |Z|) over the previous
+// state (partials) + coef * eta * max_j |D[j, c]| (a bound on the new |Z|: the all-rows map is a
+// convex combination, the block correction adds at most coef * eta * |D|)
+__global__ __launch_bounds__(256) void fused_scale_kernel(int nwg, int k, const float* __restrict__ part,
+                                                          int64_t b, const double* __restrict__ D,
+                                                          const IterScalars* __restrict__ sc,
+                                                          double coef, float* __restrict__ scale) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  double m = 0.0;
+  for (int w = threadIdx.x; w < nwg; w += 256) {
+    const double a = part[((int64_t)w * 2 + 0) * k + c], z = part[((int64_t)w * 2 + 1) * k + c];
+    m = fmax(m, fmax(a, z));
+  }
+  double dm = 0.0;
+  for (int64_t j = threadIdx.x; j < b; j += 256) dm = fmax(dm, fabs(D[j * k + c]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double mall = red[0];
+  __syncthreads();
+  red[threadIdx.x] = dm;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double bound = mall + coef * fabs(sc->eta) * red[0];
+    float sv = 1.0f;
+    if (bound > 0.0 && isfinite(bound)) {
+      int ex;
+      frexp(bound, &ex);  // bound = f 2^ex, f in [0.5, 1)
+      int p = ex - 14;
+      if (p < -60) p = -60;
+      sv = ldexpf(1.0f, p);
+    }
+    scale[c] = sv;
+  }
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void nesterov_pack_kernel(
+    int64_t n, int k, int64_t ntiles, float* __restrict__ V, float* __restrict__ Z,
+    const int64_t* __restrict__ pos, uint32_t stamp, const double* __restrict__ D,
+    const IterScalars* __restrict__ sc, double beta, double gamma, double alpha, int z_next,
+    int accel, void* __restrict__ W, DT wt, const float* __restrict__ scale, int nq,
+    half8* __restrict__ packed, float* __restrict__ part) {
+  __shared__ float zt[TILE * 128];
+  __shared__ unsigned int mv[128], mz[128];
+  const int tid = threadIdx.x;
+  for (int c = tid; c < k; c += 256) mv[c] = mz[c] = 0u;
+  const double eta = sc->eta;
+  const double cz = accel ? (z_next ? alpha * gamma + 1.0 - alpha : 1.0 - alpha) : 1.0;
+  const int words = WIDE ? nq * 128 : nq * 64;  // half8 words of one packed tile
+  for (int64_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
+    __syncthreads();  // the previous tile's packing has read zt
+    for (int e = tid; e < TILE * k; e += 256) {
+      const int64_t i = T * TILE + e / k;
+      const int c = e % k;
+      float zo = 0.0f;
+      if (i < n) {
+        const int64_t g = i * k + c;
+        const double v = (double)V[g], z = (double)Z[g];
+        double vn = v, zn = z, w = z;
+        if (accel) {
+          vn = beta * v + (1.0 - beta) * z;
+          zn = alpha * (z_next ? vn : v) + (1.0 - alpha) * z;
+        }
+        const int64_t p = pos[i];
+        if ((uint32_t)((uint64_t)p >> 32) == stamp) {
+          const double st = eta * D[(int64_t)(p & 0xffffffffLL) * k + c];
+          if (accel) vn -= gamma * st;
+          zn -= cz * st;
+          w -= st;
+        }
+        if (accel) {
+          V[g] = (float)vn;
+          atomicMax(&mv[c], __float_as_uint(fabsf((float)vn)));
+        }
+        Z[g] = (float)zn;
+        zo = (float)zn;
+        atomicMax(&mz[c], __float_as_uint(fabsf(zo)));
+        if (W) {
+          if (wt == DT::F64) static_cast<double*>(W)[g] = w;
+          else static_cast<float*>(W)[g] = (float)w;
+        }
+      }
+      zt[(e / k) * k + c] = zo;
+    }
+    __syncthreads();
+    for (int e = tid; e < words; e += 256) {
+      const int lane = e % 64;
+      half8 h;
+      if constexpr (WIDE) {
+        const int t = (e / 64) % 2, q = e / 128;
+        const int rhs = q * 32 + lane % 32;
+        const float inv = rhs < k ? 1.0f / scale[rhs] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int col = wide_col(t, 8 * (lane / 32) + j);
+          const float x = rhs < k ? zt[col * k + rhs] : 0.0f;
+          h[j] = (_Float16)(rhs < k ? (float)((double)x * (double)inv) : 0.0f);
+        }
+        packed[((T * nq + q) * 2 + t) * 64 + lane] = h;
+      } else {
+        const int q = e / 64;
+        const int rhs = q * 16 + lane % 16;
+        const float inv = rhs < k ? 1.0f / scale[rhs] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int col = slot_col(lane, m);
+          const float x = rhs < k ? zt[col * k + rhs] : 0.0f;
+          h[m] = (_Float16)(rhs < k ? (float)((double)x * (double)inv) : 0.0f);
+        }
+        packed[(T * nq + q) * 64 + lane] = h;
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < k; c += 256) {
+    part[((int64_t)blockIdx.x * 2 + 0) * k + c] = __uint_as_float(accel ? mv[c] : mz[c]);
+    part[((int64_t)blockIdx.x * 2 + 1) * k + c] = __uint_as_float(mz[c]);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- batches
@@ -1335,8 +1571,9 @@ adasap_status_t mfma_product_packed(const MfmaPack& pk, const int64_t* ridx, int
                                     const RhsPacked& rp, int k, void* out, DT ot,
                                     const KbEpilogue& ep, MfmaWork& w, hipStream_t s) {
   RhsDesc rd{rp.mode, rp.nq, rp.p, rp.scale};
+  if (w.wait_ev) ADASAP_HIP(hipStreamWaitEvent(s, w.wait_ev, 0));
   return mk_run(pk.cols.as<half8>(), pk.ntiles, pk.rowv.as<half8>(), ridx, m, pk.d, pk.kern, rd,
-                k, out, ot, ep, w.part, s);
+                k, out, ot, ep, w.part, s, w.ev0, w.ev1, 0, w.cap_cus);
 }
 
 adasap_status_t mfma_pack_rhs_full(const MfmaPack& pk, const void* R, DT rt, int k, int mode,
@@ -1640,6 +1877,71 @@ adasap_status_t mfma_batch_residual(const MfmaBatchPack& bp, int p, const void* 
   return mk_run(bp.cols.as<half8>() + bp.col_off[p], bp.ntiles[p],
                 bp.rowv.as<half8>() + bp.row_off[p] * 8, nullptr, bp.n[p], bp.d[p], bp.kern, rd, 1,
                 res, DT::F64, ep, w.part, s, nullptr, nullptr, 2);
+}
+
+
+// ---------------------------------------------------------------- fused update launchers
+namespace {
+int fused_nwg(int64_t ntiles) { return (int)(ntiles < FU_TILES_MAX ? (ntiles > 0 ? ntiles : 1) : FU_TILES_MAX); }
+}  // namespace
+
+adasap_status_t fused_init(const MfmaPack& pk, FusedUpd& f, int k, const float* V, const float* Z,
+                           MfmaWork& w, hipStream_t s) {
+  if (k < 1 || k > 128) {
+    set_error("the fused update packs 1 to 128 right-hand sides");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  const int mode = (k > 16 && k <= 64) ? MODE_F16W : MODE_F16;
+  f.nwg = fused_nwg(pk.ntiles);
+  ADASAP_TRY(f.part.ensure((size_t)f.nwg * 2 * k * sizeof(float)));
+  if (!f.pos.p || f.pos.bytes < (size_t)pk.n * sizeof(int64_t)) {
+    ADASAP_TRY(f.pos.ensure((size_t)pk.n * sizeof(int64_t)));
+    ADASAP_HIP(hipMemsetAsync(f.pos.p, 0xff, (size_t)pk.n * sizeof(int64_t), s));
+  }
+  RhsDesc rd;
+  ADASAP_TRY(pack_rhs(Z, DT::F32, pk.n, k, k, nullptr, pk.ntiles, mode, f.packed, f.scale, w.tmp, rd, s));
+  f.mode = rd.mode;
+  f.nq = rd.nq;
+  hipLaunchKernelGGL(vzmax_partial_kernel, dim3(f.nwg), dim3(256), 0, s, pk.n, k, pk.ntiles, V, Z,
+                     f.part.as<float>());
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+RhsPacked fused_rhs(const FusedUpd& f) {
+  RhsPacked rp;
+  rp.mode = f.mode;
+  rp.nq = f.nq;
+  rp.p = f.packed.p;
+  rp.scale = f.scale.as<float>();
+  return rp;
+}
+
+adasap_status_t fused_update(const MfmaPack& pk, FusedUpd& f, int k, const int64_t* B, int64_t b,
+                             const double* D, const IterScalars* sc, const NestCoef& c, float* V,
+                             float* Z, void* W, DT wt, hipStream_t s) {
+  ++f.stamp;
+  if (f.stamp == 0xffffffffu) f.stamp = 1;  // all ones marks rows never sampled
+  hipLaunchKernelGGL(pos_scatter_kernel, dim3((unsigned)((b + 255) / 256)), dim3(256), 0, s, b, B,
+                     f.stamp, f.pos.as<int64_t>());
+  ADASAP_LAUNCH_CHECK();
+  const double cz = c.accel ? (c.z_uses_v_next ? c.alpha * c.gamma + 1.0 - c.alpha : 1.0 - c.alpha) : 1.0;
+  const double coef = c.accel ? (c.gamma > cz ? c.gamma : cz) : 1.0;
+  hipLaunchKernelGGL(fused_scale_kernel, dim3(k), dim3(256), 0, s, f.nwg, k, f.part.as<float>(), b, D,
+                     sc, coef, f.scale.as<float>());
+  ADASAP_LAUNCH_CHECK();
+  if (f.mode == MODE_F16W)
+    hipLaunchKernelGGL(nesterov_pack_kernel<true>, dim3(f.nwg), dim3(256), 0, s, pk.n, k, pk.ntiles, V,
+                       Z, f.pos.as<int64_t>(), f.stamp, D, sc, c.beta, c.gamma, c.alpha,
+                       c.z_uses_v_next, c.accel, W, wt, f.scale.as<float>(), f.nq,
+                       f.packed.as<half8>(), f.part.as<float>());
+  else
+    hipLaunchKernelGGL(nesterov_pack_kernel<false>, dim3(f.nwg), dim3(256), 0, s, pk.n, k, pk.ntiles,
+                       V, Z, f.pos.as<int64_t>(), f.stamp, D, sc, c.beta, c.gamma, c.alpha,
+                       c.z_uses_v_next, c.accel, W, wt, f.scale.as<float>(), f.nq,
+                       f.packed.as<half8>(), f.part.as<float>());
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
 }
 
 int mfma_mode_f16() { return MODE_F16; }

@@ -74,8 +74,12 @@ struct adasap_handle_s {
   MfmaPack pack;  // packed coordinates for the matrix-core kernel
   // workspace
   DevBuf V, Z, Bdev, XB, G, D, Om, Ysk, Mo, Qo, Rinv, H, evals, Vr, T, S, cinv, cisq, Bm, U, rot;
+  DevBuf Hx, Linv;  // exact block projection: factor of K_BB + lambda I, diagonal-block inverses
   DevBuf vv, ww, uu, zz, coef, part_kb, part_g, part_d, scb, tail, res, rhs, delta_w, tmp, colq;
   MfmaWork mw;    // matrix-core scratch of the main stream
+  // MIXED accelerated solves: the Nesterov update packs the next Z for Step I in the same pass
+  bool fused = false;
+  FusedUpd fu;
   MfmaWork mw2;   // matrix-core scratch of the second stream (sketch, powering)
   DevBuf part_kb2, part_g2, coef2;  // second-stream scratch
   hipStream_t s2 = nullptr;         // second stream (default priority)
@@ -147,8 +151,14 @@ adasap_status_t validate(const adasap_config_t* c, int64_t n, int d, int k) {
   if (d < 1 || d > 64) return invalid("d must be in [1, 64]");
   if (k < 1 || k > 128) return invalid("k must be in [1, 128]");
   if (c->block_size < 1 || c->block_size > n) return invalid("block size must be in [1, n]");
-  if (c->precond != ADASAP_PRECOND_NYSTROM && c->precond != ADASAP_PRECOND_IDENTITY)
+  if (c->precond != ADASAP_PRECOND_NYSTROM && c->precond != ADASAP_PRECOND_IDENTITY &&
+      c->precond != ADASAP_PRECOND_EXACT)
     return invalid("unknown preconditioner");
+  if (c->precond == ADASAP_PRECOND_EXACT && c->block_size > 16384)
+    return invalid("the exact block projection needs b <= 16384 (a b x b float64 factor)");
+  if (c->precond == ADASAP_PRECOND_EXACT && c->precision == ADASAP_MIXED)
+    return invalid("the exact block projection runs with FP64 or FP32 products (its unit step "
+                   "amplifies the float16 error of MIXED products by up to 1/lambda)");
   if (c->precond == ADASAP_PRECOND_NYSTROM &&
       (c->rank < 1 || c->rank > 128 || c->rank > c->block_size))
     return invalid("rank must be in [1, min(b, 128)]");
@@ -300,6 +310,7 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   const DT gt = at_w ? h->dtype : h->st;
   if (h->use_mfma) {
     const int ring = adasap_handle_s::KEV_RING;
+    const bool fz = h->fused && !at_w;
     if (h->kev.empty()) {
       for (int e = 0; e < 2 * ring; ++e) {
         hipEvent_t ev;
@@ -318,7 +329,25 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
     h->mw.ev1 = h->kev[2 * slot + 1];
     h->mw.wait_ev = sketch_first ? h->ev_sketch : nullptr;
     ++h->kev_used;
-    const adasap_status_t pst = block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s);
+    adasap_status_t pst;
+    if (fz) {
+      // Z_t was packed by the previous update (or at the start of the sweep)
+      KbEpilogue epg;
+      epg.kscale = c.outputscale;
+      epg.E1 = gp;
+      epg.e1t = gt;
+      epg.e1idx = B;
+      epg.lde1 = k;
+      epg.a1 = c.lambda;
+      epg.E2 = rhs;
+      epg.e2t = rhst;
+      epg.e2idx = B;
+      epg.lde2 = k;
+      epg.a2 = -1.0;
+      pst = mfma_product_packed(h->pack, B, b, fused_rhs(h->fu), k, h->G.p, DT::F64, epg, h->mw, s);
+    } else {
+      pst = block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s);
+    }
     h->mw.ev0 = h->mw.ev1 = nullptr;
     h->mw.wait_ev = nullptr;
     ADASAP_TRY(pst);
@@ -326,6 +355,12 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
     ADASAP_TRY(block_gradient_h(h, B, gp, gt, rhs, rhst, h->G.as<double>(), s));
   }
 
+  const bool exact = c.precond == ADASAP_PRECOND_EXACT;
+  if (exact) {
+    // Alg. 1: the exact projection onto the block, P_B = K_BB + lambda I, unit step
+    ADASAP_TRY(exact_factor(c.kernel, h->ellk, c.outputscale, c.lambda, b, h->d, h->Xk, h->xkt, B,
+                            h->Hx.as<double>(), h->Linv.as<double>(), sc, s2));
+  }
   if (nys) {
     // Step III: Nystrom factors
     ADASAP_TRY(gram(b, r, r, h->Om.p, DT::F64, r, h->Ysk.p, DT::F64, r, h->Mo.as<double>(), nullptr,
@@ -351,9 +386,9 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   double* w = h->ww.as<double>();
   double* u = h->uu.as<double>();
   double* z = h->zz.as<double>();
-  ADASAP_TRY(normals_dev(c.seed, PURPOSE_POW + off, (uint64_t)t, b, v, s2));
-  ADASAP_TRY(normalize_inplace(b, v, sc, h->part_d, s2));
-  for (int i = 0; i < c.power_iters; ++i) {
+  if (!exact) ADASAP_TRY(normals_dev(c.seed, PURPOSE_POW + off, (uint64_t)t, b, v, s2));
+  if (!exact) ADASAP_TRY(normalize_inplace(b, v, sc, h->part_d, s2));
+  for (int i = 0; i < (exact ? 0 : c.power_iters); ++i) {
     const double* win = v;
     if (nys) {
       ADASAP_TRY(precond_apply_h(h, 1, v, w, 1, s2, h->part_g2, h->coef2));
@@ -388,6 +423,15 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   if (nys) {
     ADASAP_TRY(precond_apply_h(h, k, h->G.as<double>(), h->D.as<double>(), 0, s, h->part_g, h->coef));
     Dp = h->D.as<double>();
+  } else if (exact) {
+    ADASAP_HIP(hipMemcpyAsync(h->D.p, h->G.p, (size_t)b * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ADASAP_TRY(exact_solve(b, k, h->Hx.as<double>(), h->Linv.as<double>(), h->D.as<double>(), s));
+    Dp = h->D.as<double>();
+  }
+  if (h->fused) {
+    // all-rows and block-row parts of the update in one pass that also packs Z_{t+1}
+    return fused_update(h->pack, h->fu, k, B, b, Dp, sc, h->nc, h->V.as<float>(), h->Z.as<float>(),
+                        Wout, h->dtype, s);
   }
   if (c.accel) ADASAP_TRY(nesterov_dense(n * k, h->V.p, h->Z.p, h->st, h->nc, Wout, h->dtype, s));
   ADASAP_TRY(nesterov_sparse(b, k, B, Dp, h->V.p, h->Z.p, h->st, h->nc, sc, c.accel ? Wout : nullptr,
@@ -477,6 +521,8 @@ adasap_status_t run_sweep(adasap_handle_t h, uint64_t off, const void* rhs, DT r
     ADASAP_HIP(hipMemsetAsync(h->tail.p, 0, (size_t)nk * sizeof(double), h->s));
   }
   const int64_t every = (c.tol > 0) ? (c.check_every > 0 ? c.check_every : T) : 0;
+  if (h->fused && T > 0)
+    ADASAP_TRY(fused_init(h->pack, h->fu, h->k, h->V.as<float>(), h->Z.as<float>(), h->mw, h->s));
   for (int64_t i = 0; i < T; ++i) {
     const int64_t t = t0 + i;
     if (tail && i >= T / 2) {
@@ -616,6 +662,30 @@ adasap_status_t residual_rows_h(adasap_handle_t h, const void* W, DT wt, const v
   return ADASAP_OK;
 }
 
+// out (m x k, handle dtype) = K(X*, X) W, enqueued on the handle's stream
+adasap_status_t predict_h(adasap_handle_t h, const void* W, int64_t m, const void* Xstar, void* out) {
+  KbEpilogue none;
+  const int kprec = h->cfg.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
+  // prediction points in the coordinates the kernel values are computed from
+  const void* Xq = Xstar;
+  DT xqt = h->dtype;
+  if (!h->inv_ell.empty()) {
+    ADASAP_TRY(h->Xq.ensure((size_t)m * h->d * 8));
+    ADASAP_TRY(scale_columns(m, h->d, Xstar, h->dtype, h->iell.as<double>(), h->Xq.as<double>(), h->s));
+    Xq = h->Xq.p;
+    xqt = DT::F64;
+  }
+  if (h->use_mfma) {
+    ADASAP_TRY(mfma_points(h->pack, Xq, xqt, m, h->rowq, h->s));
+    ADASAP_TRY(mfma_product_rows(h->pack, h->rowq.p, m, W, h->dtype, h->k, mfma_mode_f16x3(), out,
+                                 h->dtype, h->mw, h->s, h->cfg.outputscale));
+  } else {
+    ADASAP_TRY(hk_kblock(h, m, h->n, Xq, nullptr, xqt, h->Xk, W, h->dtype, h->k, h->k, out, h->dtype,
+                         h->k, none, kprec, h->s, h->part_kb));
+  }
+  return ADASAP_OK;
+}
+
 // pinned trace of per-iteration scalars for `iters` iterations
 adasap_status_t ensure_trace(adasap_handle_t h, int64_t iters) {
   if (h->sc_host_cap >= iters) return ADASAP_OK;
@@ -726,6 +796,7 @@ int64_t adasap_workspace_bytes(const adasap_config_t* cfg, int64_t n, int32_t d,
   int64_t bytes = 2 * n * k * st;                       // V, Z
   bytes += b * (8 + 8 * d + 16 * k + 24 * r + 32);      // B, X_B, G, D, Omega, Y_sk, B, U, vectors
   bytes += 8 * r * r * 8 + 8 * (int64_t)jacobi_rot_capacity((int)r);
+  if (cfg->precond == ADASAP_PRECOND_EXACT) bytes += b * b * 8 + (int64_t)exact_linv_doubles(b) * 8;
   if (cfg->precision != ADASAP_FP64 && d <= 16) bytes += mfma_pack_bytes(n, d, k);
   if (cfg->n_lengthscale == d && d > 1) bytes += n * d * 8;  // scaled copy of X
   return bytes;
@@ -807,6 +878,10 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
   ENS(uu, b * 8);
   ENS(zz, b * 8);
   ENS(scb, sizeof(IterScalars));
+  if (cfg->precond == ADASAP_PRECOND_EXACT) {
+    ENS(Hx, (size_t)b * b * 8);
+    ENS(Linv, exact_linv_doubles(b) * 8);
+  }
 #undef ENS
   if (hipHostMalloc((void**)&h->Bhost[0], b * sizeof(int64_t)) != hipSuccess ||
       hipHostMalloc((void**)&h->Bhost[1], b * sizeof(int64_t)) != hipSuccess) {
@@ -852,6 +927,7 @@ adasap_status_t adasap_create(const adasap_config_t* cfg, int64_t n, int32_t d, 
     } else if (st != ADASAP_OK) {
       return fail(st);
     }
+    h->fused = h->use_mfma && cfg->precision == ADASAP_MIXED && cfg->accel && cfg->grad_at_z;
   }
   if (hipStreamSynchronize(h->s) != hipSuccess) return fail(ADASAP_ERR_DEVICE);
   *out = h;
@@ -948,25 +1024,20 @@ adasap_status_t adasap_predict(adasap_handle_t h, const void* W, int64_t m, cons
   if (m < 0) return invalid("m must be >= 0");
   if (m == 0) return ADASAP_OK;
   if (!W || !Xstar || !out) return invalid("W, Xstar and out must be non-null device pointers");
-  KbEpilogue none;
-  const int kprec = h->cfg.precision == ADASAP_FP64 ? ADASAP_FP64 : ADASAP_FP32;
-  // prediction points in the coordinates the kernel values are computed from
-  const void* Xq = Xstar;
-  DT xqt = h->dtype;
-  if (!h->inv_ell.empty()) {
-    ADASAP_TRY(h->Xq.ensure((size_t)m * h->d * 8));
-    ADASAP_TRY(scale_columns(m, h->d, Xstar, h->dtype, h->iell.as<double>(), h->Xq.as<double>(), h->s));
-    Xq = h->Xq.p;
-    xqt = DT::F64;
-  }
-  if (h->use_mfma) {
-    ADASAP_TRY(mfma_points(h->pack, Xq, xqt, m, h->rowq, h->s));
-    ADASAP_TRY(mfma_product_rows(h->pack, h->rowq.p, m, W, h->dtype, h->k, mfma_mode_f16x3(), out,
-                                 h->dtype, h->mw, h->s, h->cfg.outputscale));
-  } else {
-    ADASAP_TRY(hk_kblock(h, m, h->n, Xq, nullptr, xqt, h->Xk, W, h->dtype, h->k, h->k, out, h->dtype,
-                         h->k, none, kprec, h->s, h->part_kb));
-  }
+  ADASAP_TRY(predict_h(h, W, m, Xstar, out));
+  ADASAP_HIP(hipStreamSynchronize(h->s));
+  return ADASAP_OK;
+}
+
+adasap_status_t adasap_posterior_samples(adasap_handle_t h, const void* W, int64_t m,
+                                         const void* Xstar, const void* prior_star, void* out) {
+  if (!h) return invalid("handle is null");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return ADASAP_OK;
+  if (!W || !Xstar || !out) return invalid("W, Xstar and out must be non-null device pointers");
+  if (h->k > 1 && !prior_star) return invalid("prior_star must be a device array of m x (k - 1)");
+  ADASAP_TRY(predict_h(h, W, m, Xstar, out));
+  ADASAP_TRY(pathwise_combine(m, h->k, prior_star, h->dtype, out, h->dtype, h->s));
   ADASAP_HIP(hipStreamSynchronize(h->s));
   return ADASAP_OK;
 }

@@ -63,23 +63,34 @@ def rff_frequencies(rs, kernel, ell, d, D):
     return Wf, c
 
 
-def rff_prior_draws(X, kernel, ell, D, nsamples, rs, chunk=1 << 16):
-    """nsamples prior function draws at the rows of X (torch tensor, any device), float64."""
-    torch = _torch()
-    n, d = X.shape
+def rff_prior_params(kernel, ell, d, D, nsamples, rs):
+    """Frequencies, phases and weights of nsamples random-feature prior functions."""
     Wf, c = rff_frequencies(rs, kernel, ell, d, D)
     theta = rs.standard_normal((D, nsamples))
+    return Wf, c, theta
+
+
+def rff_eval(X, params, chunk=1 << 16):
+    """The prior functions of rff_prior_params at the rows of X (torch, any device), float64."""
+    torch = _torch()
+    Wf, c, theta = params
+    n = X.shape[0]
     dev = X.device
     Wt = torch.as_tensor(Wf, dtype=torch.float64, device=dev)
     ct = torch.as_tensor(c, dtype=torch.float64, device=dev)
     th = torch.as_tensor(theta, dtype=torch.float64, device=dev)
-    out = torch.empty((n, nsamples), dtype=torch.float64, device=dev)
-    scale = math.sqrt(2.0 / D)
+    out = torch.empty((n, theta.shape[1]), dtype=torch.float64, device=dev)
+    scale = math.sqrt(2.0 / Wf.shape[0])
     for i0 in range(0, n, chunk):
         xb = X[i0:i0 + chunk].to(torch.float64)
-        phi = torch.cos(xb @ Wt.T + ct) * scale
-        out[i0:i0 + chunk] = phi @ th
+        out[i0:i0 + chunk] = (torch.cos(xb @ Wt.T + ct) * scale) @ th
     return out
+
+
+def rff_prior_draws(X, kernel, ell, D, nsamples, rs, chunk=1 << 16):
+    """nsamples prior function draws at the rows of X (torch tensor, any device), float64."""
+    params = rff_prior_params(kernel, ell, X.shape[1], D, nsamples, rs)
+    return rff_eval(X, params, chunk)
 
 
 def make_c1(seed=1, n=4096, d=8):
@@ -108,19 +119,33 @@ def make_c2(seed=2, n=1_000_000, d=11, ell=0.3, lam=1e-3, n_dup_centres=500, cop
     return Xt.to(dt), y.to(dt)
 
 
-def make_c3(seed=3, n=2_000_000, d=11, k=64, ell=0.5, lam=1e-2, device="cpu", dtype=None):
+def make_c3(seed=3, n=2_000_000, d=11, k=64, ell=0.5, lam=1e-2, device="cpu", dtype=None,
+            n_test=0):
     """X ~ N(0, I_d); column 0 standardised y = f*(X) + eps, columns 1.. are
-    pathwise right-hand sides f_s(X) + eps_s (RBF prior, 2048 features)."""
+    pathwise right-hand sides f_s(X) + eps_s (RBF prior, 2048 features).
+
+    With n_test > 0 also returns a held-out split drawn from the same functions:
+    (X, Y, Xtest, ytest, prior_test) with ytest = f*(Xtest) + eps standardised like y and
+    prior_test = f_s(Xtest) for s = 1 .. k-1 (the prior functions of the pathwise columns)."""
     torch = _torch()
     rs = np.random.default_rng(seed)
     X = torch.as_tensor(rs.standard_normal((n, d)), device=device)
-    F = rff_prior_draws(X, "rbf", ell, 2048, k, rs)
+    params = rff_prior_params("rbf", ell, d, 2048, k, rs)
+    F = rff_eval(X, params)
     eps = torch.as_tensor(rs.standard_normal((n, k)), device=device) * math.sqrt(lam)
     Y = F + eps
     y0 = Y[:, 0]
-    Y[:, 0] = (y0 - y0.mean()) / y0.std()
+    mu, sd = y0.mean(), y0.std()
+    Y[:, 0] = (y0 - mu) / sd
     dt = dtype or torch.float32
-    return X.to(dt), Y.to(dt)
+    if n_test <= 0:
+        return X.to(dt), Y.to(dt)
+    rt = np.random.default_rng(seed + 7777)
+    Xt = torch.as_tensor(rt.standard_normal((n_test, d)), device=device)
+    Ft = rff_eval(Xt, params)
+    yt = (Ft[:, 0] + math.sqrt(lam) * torch.as_tensor(rt.standard_normal(n_test), device=device)
+          - mu) / sd
+    return X.to(dt), Y.to(dt), Xt.to(dt), yt.to(dt), Ft[:, 1:].contiguous().to(dt)
 
 
 def c4_problem_sizes(seed=4, count=256, nmin=2000, nmax=65536, dmin=4, dmax=16,
@@ -224,3 +249,19 @@ def ws_init_params(seed, sizes):
         parts.append(rs.uniform(-a, a, fan_out * fan_in))
         parts.append(np.zeros(fan_out))
     return np.concatenate(parts)
+
+
+def bo_target(seed, d=8, ell=2.0, features=5000):
+    """Black-box objective of the Bayesian-optimisation workload: one Matern-3/2 prior function
+    on [0, 1]^d from `features` random features (evaluate with rff_eval)."""
+    return rff_prior_params("matern32", ell, d, features, 1, np.random.default_rng(seed))
+
+
+def bo_initial(seed, n0, d=8, noise=1e-6, target=None, device="cpu"):
+    """n0 points uniform on [0, 1]^d and their noisy objective values (float64 torch)."""
+    torch = _torch()
+    rs = np.random.default_rng(seed)
+    X = torch.as_tensor(rs.uniform(0.0, 1.0, (n0, d)), device=device)
+    y = rff_eval(X, target)[:, 0] + math.sqrt(noise) * torch.as_tensor(rs.standard_normal(n0),
+                                                                     device=device)
+    return X, y

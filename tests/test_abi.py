@@ -116,3 +116,14 @@ def test_warm_start_param_count_and_config_validation(hlib):
         h = ctypes.c_void_p()
         st = hlib.cdll.adasap_ws_create(ctypes.byref(bad), fake, fake, fake, None, ctypes.byref(h))
         assert st == 1 and not h.value, (field, value)
+
+
+def test_exact_projection_rejects_mixed_precision(hlib):
+    cfg = hlib.config(block_size=100, rank=1, precond="exact", precision="mixed")
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert hlib.cdll.adasap_create(ctypes.byref(cfg), 1000, 4, 1, fake, fake, 0, None,
+                                   ctypes.byref(h)) == 1
+    big = hlib.config(block_size=16385, rank=1, precond="exact", precision="fp64")
+    assert hlib.cdll.adasap_create(ctypes.byref(big), 20000, 4, 1, fake, fake, 1, None,
+                                   ctypes.byref(h)) == 1

@@ -362,3 +362,48 @@ def test_bad_lengthscales_are_rejected(lib):
         with pytest.raises(AdasapError) as e:
             lib.create(lib.config(block_size=50, rank=10, precision="fp64", **kw), dev(X), dev(Y))
         assert e.value.status == 1
+
+
+@pytest.mark.parametrize("b,accel", [(100, 0), (200, 0), (130, 1), (64, 0)])
+def test_exact_block_projection_matches_oracle(lib, b, accel):
+    # precond EXACT: P_B = K_BB + lambda I factored in float64 (blocked Cholesky, panels of 64
+    # columns: b = 100, 130 and 200 have ragged last panels), unit step.  accel = 0 is SAP
+    # (Alg. 1), accel = 1 the accelerated step around the exact projection
+    n, d, k, lam, ell, T = 700, 3, 2, 0.03, 0.9, 12
+    X, Y = inputs.make_small(91, n, d, k)
+    Wo, info = OA.adasap(X, Y, OK.MATERN32, ell, lam, b, 1, T, 5,
+                         precond="sap" if not accel else "exact")
+    Wg, rep, tr, h = _gpu_solve(lib, X, Y, kernel="matern32", lengthscale=ell, lam=lam, block_size=b,
+                                rank=1, max_iters=T, seed=5, precision="fp64", precond="exact",
+                                accel=accel)
+    h.close()
+    assert np.all(tr["eta"] == 1.0) and np.allclose(info["eta"], 1.0, rtol=1e-12)
+    delta = knorm_diff(X, Wg, Wo, Y, OK.MATERN32, ell, lam)
+    assert delta <= 1e-6, delta
+
+
+def test_exact_projection_with_full_block_solves_in_one_step(lib):
+    n, k, lam = 160, 3, 0.02
+    X, Y = inputs.make_small(92, n, 4, k)
+    Wg, rep, tr, h = _gpu_solve(lib, X, Y, kernel="rbf", lengthscale=1.1, lam=lam, block_size=n,
+                                rank=1, max_iters=1, seed=1, precision="fp64", precond="exact",
+                                accel=0)
+    rr, _ = h.residual(dev(Wg))
+    h.close()
+    assert rr < 1e-11, rr
+    assert OL.relres(X, Y, Wg, OK.RBF, 1.1, lam)[0] < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp32"])
+def test_exact_projection_reduced_precision(lib, precision):
+    # the factor is float64 from the float32 coordinates; Step I runs at the handle's precision
+    # (MIXED is rejected for this preconditioner: measured delta 1.1e-3 after 10 SAP steps)
+    n, d, k, lam, ell, b, T = 900, 5, 2, 0.05, 1.2, 150, 10
+    X, Y = inputs.make_small(93, n, d, k)
+    X, Y = X.astype(np.float32).astype(np.float64), Y.astype(np.float32).astype(np.float64)
+    Wo, _ = OA.adasap(X, Y, OK.RBF, ell, lam, b, 1, T, 2, precond="sap")
+    Wg, rep, tr, h = _gpu_solve(lib, X, Y, dtype=torch.float32, kernel="rbf", lengthscale=ell,
+                                lam=lam, block_size=b, rank=1, max_iters=T, seed=2,
+                                precision=precision, precond="exact", accel=0)
+    h.close()
+    assert knorm_diff(X, Wg, Wo, Y, OK.RBF, ell, lam) <= 1e-3
