@@ -299,6 +299,22 @@ adasap_status_t adasap_kblock_matmul(int32_t kernel, double lengthscale, int32_t
                                      const void* Xc, const void* R, void* out, int32_t dtype,
                                      void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): adasap_kblock_matmul in FP64 or FP32
+ * precision with no allocation of any kind.  Arguments and results are those of
+ * adasap_kblock_matmul (MIXED is rejected with ADASAP_ERR_INVALID_ARG).  The split partial
+ * sums of the product live in a fixed 32 MiB device array of the library (each GPU the
+ * library runs on holds its own copy until the process ends), so m * k * (8 for FP64, 4 for
+ * FP32) must not exceed 32 MiB (ADASAP_ERR_INVALID_ARG otherwise, before any device work).
+ * Every call on one GPU shares that array: calls that overlap in time on one GPU (on
+ * different streams or host threads) race and must be serialised by the caller; calls in
+ * order on one stream are safe.  Unlike adasap_kblock_matmul the call only enqueues the
+ * work on `stream` and returns without synchronising. */
+adasap_status_t adasap_kblock_matmul_noalloc(int32_t kernel, double lengthscale, int32_t precision,
+                                             int64_t m, int64_t n, int32_t d, int32_t k,
+                                             const void* Xr, const void* Xc, const void* R,
+                                             void* out, int32_t dtype, void* stream);
+
 /* Randomized Nystrom factors of a b x b PSD matrix from its sketch (Appendix,
  * Alg. NysApprox): Ysk = M Omega and Omega (device, b x r, float64).  Outputs
  * (device, float64): U (b x r, orthonormal columns), S (r, descending, >= 0) and

@@ -105,6 +105,8 @@ _SIGNATURES = {
     "adasap_sample_block": (_I32, [_U64, _U64, _U64, _I64, _I64, _P]),
     "adasap_normals": (_I32, [_U64, _U64, _U64, _I64, _P, _P]),
     "adasap_kblock_matmul": (_I32, [_I32, _D, _I32, _I64, _I64, _I32, _I32, _P, _P, _P, _P, _I32, _P]),
+    "adasap_kblock_matmul_noalloc": (_I32, [_I32, _D, _I32, _I64, _I64, _I32, _I32, _P, _P, _P, _P,
+                                            _I32, _P]),
     "adasap_nystrom": (_I32, [_I64, _I32, _P, _P, _D, _P, _P, _P, _P]),
     "adasap_precond_apply": (_I32, [_I64, _I32, _I32, _P, _P, _D, _I32, _P, _P, _P]),
     "adasap_solve_batch": (_I32, [ctypes.POINTER(Problem), _I32, ctypes.POINTER(Config), _I32, _P,
@@ -262,6 +264,19 @@ class Library:
                                                   Xr.shape[1], R2.shape[1], _ptr(Xr), _ptr(Xc),
                                                   _ptr(R2), _ptr(out), _dtype_code(Xr), _stream()))
         return out if R.dim() == 2 else out[:, 0]
+
+    def kblock_matmul_noalloc(self, kernel, ell, precision, Xr, Xc, R, out):
+        """The kernel-block product with no allocation, into the caller's `out` (enqueued on
+        torch's current stream, not synchronised)."""
+        _check_dev(Xr, Xc, R, out)
+        R2 = R if R.dim() == 2 else R.view(-1, 1)
+        kernel = KERNELS.get(kernel, kernel)
+        precision = PRECISIONS.get(precision, precision)
+        self.check(self.cdll.adasap_kblock_matmul_noalloc(kernel, ell, precision, Xr.shape[0],
+                                                          Xc.shape[0], Xr.shape[1], R2.shape[1],
+                                                          _ptr(Xr), _ptr(Xc), _ptr(R2), _ptr(out),
+                                                          _dtype_code(Xr), _stream()))
+        return out
 
     def predictive_metrics(self, samples, ystar, lam):
         """(test RMSE, mean NLL) of [posterior mean | samples] against ystar."""

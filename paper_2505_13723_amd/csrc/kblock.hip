@@ -8,6 +8,11 @@
 // coordinate differences and accumulates KC right-hand-side columns in registers.  The
 // column range is split over gridDim.y workgroups; partial results are summed in a fixed
 // order by a second kernel that also applies the epilogue, so results are deterministic.
+#include <climits>
+#include <cmath>
+#include <mutex>
+#include <string>
+
 #include "internal.h"
 #include "kfun.h"
 
@@ -235,6 +240,67 @@ adasap_status_t ratio_stats(int64_t rows, int k, const double* A, const double* 
   return ADASAP_OK;
 }
 
+namespace {
+
+// Launch plan of a kernel-block product: workgroups of KB_ROWS rows (gx), right-hand-side
+// groups of kc columns (gz) and column splits of cps columns.  Enough workgroups to fill 256
+// CUs several times, at least one tile per split, and at most max_splits splits.
+struct KbPlan {
+  int dmax, kc;
+  int64_t gx, gz, splits, cps;
+};
+
+KbPlan kb_plan(int64_t m, int64_t n, int d, int k, int64_t max_splits) {
+  KbPlan pl;
+  pl.dmax = d <= 16 ? 16 : 64;
+  pl.kc = k == 1 ? 1 : (k <= 4 ? 4 : 16);
+  pl.gx = (m + KB_ROWS - 1) / KB_ROWS;
+  pl.gz = (k + pl.kc - 1) / pl.kc;
+  pl.splits = 0;
+  pl.cps = KB_BN;
+  if (n > 0) {
+    int64_t sp = (2048 + pl.gx * pl.gz - 1) / (pl.gx * pl.gz);
+    const int64_t tiles = (n + KB_BN - 1) / KB_BN;
+    if (sp > tiles) sp = tiles;
+    if (sp > max_splits) sp = max_splits;
+    if (sp < 1) sp = 1;
+    pl.cps = (n + sp - 1) / sp;
+    pl.cps = (pl.cps + KB_BN - 1) / KB_BN * KB_BN;
+    pl.splits = (n + pl.cps - 1) / pl.cps;
+  }
+  return pl;
+}
+
+// the product into `part` (splits x m x k of the arithmetic type) and the fixed-order
+// reduction with the epilogue; allocates nothing
+adasap_status_t kb_launch(const KbPlan& pl, int kern, double ell, int prec, int64_t m, int64_t n,
+                          int d, int k, const void* Xr, const int64_t* ridx, DT xt, const void* Xc,
+                          const void* R, DT rt, int64_t ldr, void* out, DT ot, int64_t ldo,
+                          const KbEpilogue& ep, void* part, hipStream_t s) {
+  if (pl.splits > 0) {
+    const dim3 grid((unsigned)pl.gx, (unsigned)pl.splits, (unsigned)pl.gz);
+    if (prec == ADASAP_FP64)
+      dispatch_kern<double>(kern, pl.dmax, pl.kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr,
+                            k, static_cast<double*>(part), pl.cps, kernel_param(kern, ell));
+    else
+      dispatch_kern<float>(kern, pl.dmax, pl.kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k,
+                           static_cast<float*>(part), pl.cps, (float)kernel_param(kern, ell));
+    ADASAP_LAUNCH_CHECK();
+  }
+  // no columns: zero splits, so the reduction writes the epilogue alone
+  const unsigned rb = (unsigned)((m * k + 255) / 256);
+  if (prec == ADASAP_FP64)
+    hipLaunchKernelGGL(kblock_reduce_kernel<double>, dim3(rb), dim3(256), 0, s,
+                       static_cast<const double*>(part), (int)pl.splits, m, k, ep, out, ot, ldo);
+  else
+    hipLaunchKernelGGL(kblock_reduce_kernel<float>, dim3(rb), dim3(256), 0, s,
+                       static_cast<const float*>(part), (int)pl.splits, m, k, ep, out, ot, ldo);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
+}  // namespace
+
 adasap_status_t kblock_valu(int kern, double ell, int prec, int64_t m, int64_t n, int d, int k,
                             const void* Xr, const int64_t* ridx, DT xt, const void* Xc,
                             const void* R, DT rt, int64_t ldr, void* out, DT ot, int64_t ldo,
@@ -244,44 +310,94 @@ adasap_status_t kblock_valu(int kern, double ell, int prec, int64_t m, int64_t n
     set_error("kblock_valu: d must be in [1, 64]");
     return ADASAP_ERR_INVALID_ARG;
   }
-  const int dmax = d <= 16 ? 16 : 64;
-  const int kc = k == 1 ? 1 : (k <= 4 ? 4 : 16);
-  const int64_t gx = (m + KB_ROWS - 1) / KB_ROWS;
-  const int64_t gz = (k + kc - 1) / kc;
-  // enough workgroups to fill 256 CUs several times, but at least one tile per split
-  int64_t splits = 1, cps = KB_BN;
-  if (n > 0) {
-    splits = (2048 + gx * gz - 1) / (gx * gz);
-    const int64_t max_splits = (n + KB_BN - 1) / KB_BN;
-    if (splits > max_splits) splits = max_splits;
-    if (splits < 1) splits = 1;
-    cps = (n + splits - 1) / splits;
-    cps = (cps + KB_BN - 1) / KB_BN * KB_BN;
-    splits = (n + cps - 1) / cps;
-  }
+  const KbPlan pl = kb_plan(m, n, d, k, INT64_MAX);
   const size_t tsz = prec == ADASAP_FP64 ? 8 : 4;
-  ADASAP_TRY(part.ensure((size_t)splits * m * k * tsz));
-  const dim3 grid((unsigned)gx, (unsigned)splits, (unsigned)gz);
-  if (n == 0) {
-    ADASAP_HIP(hipMemsetAsync(part.p, 0, (size_t)m * k * tsz, s));
-  } else if (prec == ADASAP_FP64) {
-    dispatch_kern<double>(kern, dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k,
-                          part.as<double>(), cps, kernel_param(kern, ell));
-  } else {
-    dispatch_kern<float>(kern, dmax, kc, grid, s, Xr, ridx, xt, m, Xc, n, d, R, rt, ldr, k,
-                         part.as<float>(), cps, (float)kernel_param(kern, ell));
-  }
-  ADASAP_LAUNCH_CHECK();
-  const int64_t total = m * k;
-  const unsigned rb = (unsigned)((total + 255) / 256);
-  if (prec == ADASAP_FP64)
-    hipLaunchKernelGGL(kblock_reduce_kernel<double>, dim3(rb), dim3(256), 0, s,
-                       part.as<double>(), (int)splits, m, k, ep, out, ot, ldo);
-  else
-    hipLaunchKernelGGL(kblock_reduce_kernel<float>, dim3(rb), dim3(256), 0, s, part.as<float>(),
-                       (int)splits, m, k, ep, out, ot, ldo);
-  ADASAP_LAUNCH_CHECK();
-  return ADASAP_OK;
+  ADASAP_TRY(part.ensure((size_t)(pl.splits > 0 ? pl.splits : 1) * m * k * tsz));
+  return kb_launch(pl, kern, ell, prec, m, n, d, k, Xr, ridx, xt, Xc, R, rt, ldr, out, ot, ldo, ep,
+                   part.p, s);
 }
 
+// ---- the kernel-block product with no allocation ---------------------------------------------
+// The split partial sums live in this file-scope device array.  Host code never uses its name
+// as an address: each device's copy is looked up once with hipGetSymbolAddress and that
+// pointer is what the kernels receive.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+adasap_status_t scratch_address(void** out) {
+  int dev = 0;
+  ADASAP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("device index out of range for the fixed scratch table");
+    return ADASAP_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress of the fixed scratch failed: ") + hipGetErrorString(e));
+      return ADASAP_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ADASAP_OK;
+}
+}  // namespace
+
 }  // namespace adasap
+
+using namespace adasap;
+
+extern "C" adasap_status_t adasap_kblock_matmul_noalloc(int32_t kernel, double lengthscale,
+                                                        int32_t precision, int64_t m, int64_t n,
+                                                        int32_t d, int32_t k, const void* Xr,
+                                                        const void* Xc, const void* R, void* out,
+                                                        int32_t dtype, void* stream) {
+  if (kernel < 0 || kernel > 3) {
+    set_error("unknown kernel");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  if (!(lengthscale > 0) || !std::isfinite(lengthscale)) {
+    set_error("lengthscale must be finite and > 0");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  if (precision != ADASAP_FP64 && precision != ADASAP_FP32) {
+    set_error("the no-allocation product runs in FP64 or FP32 precision");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  if (m < 0 || n < 0 || d < 1 || d > 64 || k < 1 || k > 128) {
+    set_error("need m, n >= 0, 1 <= d <= 64 and 1 <= k <= 128");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  if (dtype != ADASAP_DTYPE_F32 && dtype != ADASAP_DTYPE_F64) {
+    set_error("unknown dtype");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  const size_t tsz = precision == ADASAP_FP64 ? 8 : 4;
+  if ((size_t)m * (size_t)k * tsz > NOALLOC_SCRATCH_BYTES) {
+    set_error("m * k * element size exceeds the fixed scratch of " +
+              std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  if (m == 0) return ADASAP_OK;
+  if (!Xr || !out || (n > 0 && (!Xc || !R))) {
+    set_error("null device pointer");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  void* part = nullptr;
+  ADASAP_TRY(scratch_address(&part));
+  const int64_t fit = (int64_t)(NOALLOC_SCRATCH_BYTES / ((size_t)m * k * tsz));
+  const KbPlan pl = kb_plan(m, n, d, k, fit);
+  const DT t = dtype == ADASAP_DTYPE_F64 ? DT::F64 : DT::F32;
+  KbEpilogue none;
+  return kb_launch(pl, kernel, lengthscale, precision, m, n, d, k, Xr, nullptr, t, Xc, R, t, k, out,
+                   t, k, none, part, static_cast<hipStream_t>(stream));
+}
+

@@ -118,6 +118,18 @@ def test_warm_start_param_count_and_config_validation(hlib):
         assert st == 1 and not h.value, (field, value)
 
 
+def test_noalloc_product_validates_before_device_work(hlib):
+    fake = ctypes.c_void_p(0x1000)
+    f = hlib.cdll.adasap_kblock_matmul_noalloc
+    # beyond the fixed 32 MiB scratch: 32769 rows x 128 columns x 8 bytes
+    assert f(0, 1.0, 0, 32769, 10, 3, 128, fake, fake, fake, fake, 1, None) == 1
+    assert "scratch" in hlib.last_error()
+    assert f(0, 1.0, 2, 10, 10, 3, 1, fake, fake, fake, fake, 1, None) == 1   # MIXED
+    assert f(0, 0.0, 0, 10, 10, 3, 1, fake, fake, fake, fake, 1, None) == 1   # lengthscale
+    assert f(0, 1.0, 0, 10, 10, 65, 1, fake, fake, fake, fake, 1, None) == 1  # d
+    assert f(0, 1.0, 0, 0, 10, 3, 1, None, None, None, None, 1, None) == 0    # empty: nothing to do
+
+
 def test_exact_projection_rejects_mixed_precision(hlib):
     cfg = hlib.config(block_size=100, rank=1, precond="exact", precision="mixed")
     h = ctypes.c_void_p()
