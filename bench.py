@@ -86,6 +86,11 @@ def main():
     ap.add_argument("--bo-acq", type=int, default=1000, help="acquisitions per BO step")
     ap.add_argument("--bo-seeds", type=int, default=1, help="objective functions per lengthscale")
     ap.add_argument("--bo-passes", type=int, default=10, help="ADASAP data passes per solve")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default=None,
+                    help="precision of the single-problem workloads (default: the workload's)")
+    ap.add_argument("--check-rows", type=int, default=0,
+                    help="residual checks of the single-problem workloads on this many sampled rows "
+                         "(0: all rows)")
     ap.add_argument("--shape", choices=["rbf_n2m_k64", "rbf_n100m"], default="rbf_n2m_k64",
                     help="problem of the step1 workload")
     ap.add_argument("--ws-lam", type=float, default=1.0, help="noise variance of the warm workload")
@@ -365,10 +370,14 @@ def bench_single_k1(args, torch, binding, inputs):
     del y
     torch.cuda.synchronize()
 
+    prec = args.precision or w["precision"]
+    if prec == "fp64":
+        X, Y = X.double(), Y.double()
+
     def make(iters, tol=0.0, check_every=0):
         c = lib.config(kernel=w["kernel"], lengthscale=ell, lam=lam, block_size=b, rank=r,
                        max_iters=iters, tol=tol, check_every=check_every, seed=w["seed"],
-                       precision="fp32")
+                       precision=prec, check_rows=args.check_rows)
         return lib.create(c, X, Y)
 
     W = torch.zeros_like(Y)
@@ -384,7 +393,8 @@ def bench_single_k1(args, torch, binding, inputs):
     kern_ms = rep["step1_kernel_ms"] / max(1, rep["step1_launches"])
     pairs = float(b) * n
     trans = 1 if w["kernel"] == "rbf" else 2  # exp2, or sqrt and exp2 (Matern)
-    achieved = pairs * trans / (kern_ms * 1e-3) / 1e12
+    # the float64 path has no matrix-core Step-I launch to time (kern_ms = 0)
+    achieved = pairs * trans / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
     value = pairs * (2 * d + 2) / (ms_per_step * 1e-3) / 1e9
     extra = {}
     if big:
@@ -406,7 +416,8 @@ def bench_single_k1(args, torch, binding, inputs):
         extra["time_to_relres_1e-3"] = {"seconds": rep2["solve_ms"] / 1e3 if reached else None,
                                         "reached": bool(reached), "iterations": rep2["iters"],
                                         "passes": rep2["iters"] / per_pass, "relres": rep2["relres"],
-                                        "check_seconds_off_clock": rep2["check_ms"] / 1e3}
+                                        "check_seconds_off_clock": rep2["check_ms"] / 1e3,
+                                        "check_rows": args.check_rows or n}
         log("time-to-residual: %s" % json.dumps(extra["time_to_relres_1e-3"]))
     line = {
         "metric": "kernel-block GFLOP/s (Step-I flops per whole iteration), %s, 1 GPU" % args.workload,
@@ -416,11 +427,12 @@ def bench_single_k1(args, torch, binding, inputs):
         "dtype": "f32 (f16 hi/lo matrix-core distances, f32 vector K.Z), f64 Nystrom core",
         "data": "synthetic (seeded, GP prior-draw targets)",
         "config": {"workload": "%s_n%d_d%d" % (w["kernel"], n, d), "n": n, "d": d, "b": b, "r": r,
-                   "lambda": lam, "lengthscale": ell, "kernel": w["kernel"], "precision": "fp32"},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
-                     "unit": "Ttranscendental/s", "frac": round(achieved / PEAK_EXP_TPS, 4),
-                     "traffic": None, "kernel": "mk_kernel (Step-I product, float32 vector mode)",
-                     "kernel_ms": round(kern_ms, 4)},
+                   "lambda": lam, "lengthscale": ell, "kernel": w["kernel"], "precision": prec},
+        "roofline": None if kern_ms <= 0 else {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
+            "unit": "Ttranscendental/s", "frac": round(achieved / PEAK_EXP_TPS, 4),
+            "traffic": None, "kernel": "mk_kernel (Step-I product, float32 vector mode)",
+            "kernel_ms": round(kern_ms, 4)},
         "cpu_baseline": None,
     }
     line.update(extra)

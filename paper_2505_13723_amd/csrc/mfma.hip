@@ -852,9 +852,10 @@ __device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const
       });
     } else {
       // Interleaved within the wave: row tile 1's distance MFMAs issue beside row tile 0's
-      // exponentials and conversions, and row tile 0's K Z MFMAs beside row tile 1's, so that
-      // the matrix cores and the vector ALUs work at the same time.  Scheduling barriers keep
-      // the compiler from regrouping the chunks.
+      // exponentials and conversions, and row tile 0's K Z MFMAs beside row tile 1's;
+      // scheduling barriers keep the compiler from regrouping the chunks.  Measured at the
+      // 2M-point, 64-column shape: 7.28 ms per launch against 6.7-6.9 ms for the deferred
+      // form above, which the kernel instantiates.
       f16v D0, D1;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {

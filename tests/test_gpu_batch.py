@@ -65,3 +65,42 @@ def test_batch_rejects_bad_problems(lib):
         lib.solve_batch(lib.config(block_size=5000, rank=16, precision="fp32"), Xd, Yd, Wd, [1.0])
     with pytest.raises(AdasapError):  # float64 precision is not batched
         lib.solve_batch(lib.config(block_size=100, rank=16, precision="fp64"), Xd, Yd, Wd, [1.0])
+
+
+@pytest.mark.timeout(600)
+def test_batch_of_32_benchmark_problems_matches_oracle(lib):
+    # 32 problems of the 256-problem benchmark batch spanning its sizes (n from ~2,000 to
+    # ~65,000, d from 4 to 16, lengthscales 0.2 to 2), three rounds from W_0 = 0 with the
+    # benchmark's b = 1024, r = 64; each problem against the touched-rows oracle
+    from oracle import adasap as OA2
+    from support_delta import delta_support
+    w = inputs.WORKLOADS["c4_batched_256"]
+    ns, ds, ells = inputs.c4_problem_sizes(seed=w["seed"], count=w["count"], nmin=w["nmin"],
+                                           nmax=w["nmax"], dmin=w["dmin"], dmax=w["dmax"],
+                                           ellmin=w["ellmin"], ellmax=w["ellmax"])
+    pick = np.argsort(ns)[::8]
+    assert ns[pick].min() < 2500 and ns[pick].max() > 50000 and len(pick) == 32
+    lam, b, r, T, seed = w["lam"], w["b"], w["r"], 3, 17
+    Xs, Ys = [], []
+    for p in pick:
+        X, y = inputs.make_c4_problem(int(p), int(ns[p]), int(ds[p]), seed=w["seed"])
+        Xs.append(X.astype(np.float32).astype(np.float64))
+        Ys.append(y.astype(np.float32).astype(np.float64)[:, None])
+    Xd = [torch.as_tensor(X, dtype=torch.float32).cuda() for X in Xs]
+    Yd = [torch.as_tensor(y, dtype=torch.float32).cuda() for y in Ys]
+    Wd = [torch.zeros_like(y) for y in Yd]
+    cfg = lib.config(kernel="rbf", lam=lam, block_size=b, rank=r, max_iters=T, seed=seed,
+                     precision="fp32")
+    lib.solve_batch(cfg, Xd, Yd, Wd, [float(ells[p]) for p in pick])
+    worst = 0.0
+    for j, p in enumerate(pick):
+        S, WS, info = OA2.adasap_from_zero(Xs[j], Ys[j], OK.RBF, float(ells[p]), lam, b, r, T,
+                                           seed + j, eps_sketch=2.0 ** -23)
+        Wg = Wd[j].cpu().double().numpy()
+        outside = np.ones(Xs[j].shape[0], dtype=bool)
+        outside[S] = False
+        assert not np.any(Wg[outside])
+        d = delta_support(Xs[j], Ys[j], S, Wg[S] - WS, OK.RBF, float(ells[p]), lam, 4096, j)
+        worst = max(worst, d)
+        assert d <= 1e-3, (int(p), int(ns[p]), int(ds[p]), d)
+    print("32 batched problems: worst delta %.3e" % worst, flush=True)
