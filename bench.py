@@ -80,7 +80,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=384, help="oracle block rows per host core")
     ap.add_argument("--workload", choices=["c3", "batched", "warm", "step1", "matern32_n1m", "rbf_n100m",
-                                           "bo"], default="c3")
+                                           "bo", "matern32_precision", "tailavg", "batched_ttr", "c1"],
+                    default="c3")
     ap.add_argument("--bo-n0", type=int, default=250_000, help="initial points of the BO workload")
     ap.add_argument("--bo-steps", type=int, default=10)
     ap.add_argument("--bo-acq", type=int, default=1000, help="acquisitions per BO step")
@@ -114,6 +115,14 @@ def main():
         return bench_single_k1(args, torch, binding, inputs)
     if args.workload == "bo":
         return bench_bo(args, torch, binding)
+    if args.workload == "matern32_precision":
+        return bench_matern_precision(args, torch, binding, inputs)
+    if args.workload == "tailavg":
+        return bench_tailavg(args, torch, binding, inputs)
+    if args.workload == "batched_ttr":
+        return bench_batched_ttr(args, torch, binding, inputs)
+    if args.workload == "c1":
+        return bench_c1(args, torch, binding, inputs)
     cfgw = dict(inputs.WORKLOADS["c3_rbf_n2m_k64"])
     n, d, k = args.n, cfgw["d"], cfgw["k"]
     b, r, lam, ell = cfgw["b"], cfgw["r"], cfgw["lam"], cfgw["ell"]
@@ -319,6 +328,253 @@ def bench_batched(args, torch, binding, inputs):
                      "kernel_ms": round(kern_ms, 4), "algorithmic_exp_per_launch": pairs},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_matern_precision(args, torch, binding, inputs):
+    """The ill-conditioned Matern-3/2 problem (n = 1M with near-duplicates, lambda = 1e-3) solved
+    with the same seed at FP32 (float16 hi/lo distances on the matrix cores) and at FP64 (float64
+    distances and products), in chunks of 10 data passes continued on the same run; after each
+    chunk the float64 row certificate (2^14 rows).  If FP64 goes below the FP32 run's level,
+    the float16 distances set the floor; if both track each other, convergence is slow."""
+    w = inputs.WORKLOADS["c2_matern32_n1m"]
+    lib = binding.load()
+    n, d, b, r, lam, ell = w["n"], w["d"], w["b"], w["r"], w["lam"], w["ell"]
+    X, y = inputs.make_c2(seed=w["seed"], n=n, d=d, ell=ell, lam=lam, device="cuda")
+    Y = y[:, None].contiguous()
+    per_pass = int(math.ceil(n / b))
+    chunk = 10 * per_pass
+    out = {}
+    for prec in ("fp32", "fp64"):
+        Xp, Yp = (X.double(), Y.double()) if prec == "fp64" else (X, Y)
+        h = lib.create(lib.config(kernel="matern32", lengthscale=ell, lam=lam, block_size=b, rank=r,
+                                  max_iters=chunk, seed=w["seed"], precision=prec), Xp, Yp)
+        W = torch.zeros_like(Yp)
+        curve, secs = [], 0.0
+        for c in range(args.ttr_passes // 10):
+            rep = h.solve(W) if c == 0 else h.solve_more(W, chunk)
+            secs += rep["solve_ms"] / 1e3
+            est, _, se = h.residual_rows_f64(W, 1 << 14, 12)
+            curve.append({"passes": 10 * (c + 1), "relres_f64_rows": est, "rel_se": se,
+                          "solve_seconds": round(secs, 2)})
+            log("%s after %d passes: relres %.4e (s.e. %.1f%%), %.1f s" % (prec, 10 * (c + 1), est,
+                                                                          100 * se, secs))
+        h.close()
+        out[prec] = curve
+    line = {"metric": "relative residual vs data passes, FP32 and FP64, Matern-3/2 n=1M, 1 GPU",
+            "value": out["fp64"][-1]["relres_f64_rows"], "unit": "relres", "n_gpus": 1,
+            "steps": args.ttr_passes * per_pass, "warmup": 0, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f16 hi/lo distances) and f64",
+            "data": "synthetic (uniform points with 5% near-duplicates, Matern-3/2 prior target)",
+            "config": {"workload": "matern32_n1m_d11_precision", "n": n, "d": d, "b": b, "r": r,
+                       "lambda": lam, "lengthscale": ell},
+            "curves": out, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
+def bench_tailavg(args, torch, binding, inputs):
+    """Tail averaging with and without (appendix, impact of tail averaging): n = 1000 RBF, the
+    relative error of the posterior mean on the top-l spectral subspace, l in {10, 100, 1000},
+    ||P_l(m_hat) - P_l(m_n)||_H^2 / ||P_l(m_n)||_H^2, after 1 .. 50 data passes, for three
+    block sizes; FP64 solves through the library (tail_average flag), the subspace errors from
+    the eigendecomposition of K on the host."""
+    lib = binding.load()
+    n, d, ell, lam, seed = 1000, 3, 1.0, 1e-2, 21
+    X, Y = inputs.make_small(seed, n, d, 1)
+    Xd = torch.as_tensor(X, dtype=torch.float64).cuda()
+    Yd = torch.as_tensor(Y, dtype=torch.float64).cuda()
+    # the exact solution and the spectral basis of K (float64 kernel values on the device, as
+    # products with blocks of the identity)
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    Kh = torch.cat([lib.kblock_matmul("rbf", ell, "fp64", Xd, Xd, eye[:, j:j + 100].contiguous())
+                    for j in range(0, n, 100)], dim=1).cpu().numpy()
+    Kh = 0.5 * (Kh + Kh.T)
+    ev, U = np.linalg.eigh(Kh)
+    ev, U = ev[::-1], U[:, ::-1]
+    Wstar = np.linalg.solve(Kh + lam * np.eye(n), Y)
+
+    def sub_err(W, l):
+        a = U[:, :l].T @ (W - Wstar)[:, 0]
+        c = U[:, :l].T @ Wstar[:, 0]
+        return float(np.sum(ev[:l] * a * a) / np.sum(ev[:l] * c * c))
+
+    passes = [1, 2, 5, 10, 20, 50]
+    res = {}
+    for b in (25, 100, 400):
+        per_pass = n // b
+        for tail in (0, 1):
+            curve = []
+            for P in passes:
+                h = lib.create(lib.config(kernel="rbf", lengthscale=ell, lam=lam, block_size=b,
+                                          rank=min(b, 50), max_iters=P * per_pass, seed=seed,
+                                          precision="fp64", tail_average=tail), Xd, Yd)
+                W = torch.zeros_like(Yd)
+                h.solve(W)
+                h.close()
+                Wh = W.cpu().numpy()
+                curve.append({"passes": P, **{"err_top%d" % l: sub_err(Wh, l) for l in (10, 100, 1000)}})
+            res["b%d_%s" % (b, "tail" if tail else "last")] = curve
+            log("b=%d tail=%d: %s" % (b, tail, curve[-1]))
+    summary = {}
+    for b in (25, 100, 400):
+        for l in (10, 100, 1000):
+            last = res["b%d_last" % b][-1]["err_top%d" % l]
+            tail = res["b%d_tail" % b][-1]["err_top%d" % l]
+            summary["b%d_top%d" % (b, l)] = {"last_iterate": last, "tail_average": tail,
+                                             "tail_over_last": tail / last if last > 0 else None}
+    line = {"metric": "top-l subspace error after 50 passes, tail averaging vs last iterate, 1 GPU",
+            "value": None, "unit": "relative error", "n_gpus": 1, "steps": 50, "warmup": 0,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic (n = 1000, d = 3, sum-of-sines target)",
+            "config": {"workload": "tail_average_rbf_n1000", "n": n, "d": d, "lengthscale": ell,
+                       "lambda": lam, "blocks": [25, 100, 400]},
+            "summary": summary, "curves": res, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
+def bench_c1(args, torch, binding, inputs):
+    """The small float64 workload (n = 4096, d = 8, RBF ell = 1, lambda = rho = 1e-2, b = 256,
+    r = 64, 200 iterations, one right-hand side): the library's FP64 solve timed on the device,
+    beside the oracle's full 200-iteration run and a direct Cholesky solve on the host cores,
+    with the relative residual of each and the GPU-oracle difference
+    ||(K + lambda I)(W_gpu - W_oracle)|| / ||y||."""
+    lib = binding.load()
+    cfg = inputs.WORKLOADS["c1_fp64_n4096"]
+    X, y = inputs.make_c1(seed=cfg["seed"])
+    T = cfg["iters"]
+    Xd = torch.as_tensor(X).cuda()
+    Yd = torch.as_tensor(y[:, None]).contiguous().cuda()
+    c = lib.config(kernel="rbf", lengthscale=cfg["ell"], lam=cfg["lam"], block_size=cfg["b"],
+                   rank=cfg["r"], rho_rule=1, rho=cfg["rho"], max_iters=T, seed=cfg["seed"],
+                   precision="fp64")
+    times = []
+    for rep in range(1 + max(1, args.steps // 10)):
+        h = lib.create(c, Xd, Yd)
+        W = torch.zeros_like(Yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.solve(W)
+        torch.cuda.synchronize()
+        if rep > 0:
+            times.append(time.perf_counter() - t0)
+        relres_gpu = h.residual(W)[0]
+        h.close()
+    t_gpu = min(times)
+    log("GPU FP64: %d iterations in %.4f s, relres %.4e" % (T, t_gpu, relres_gpu))
+    base = None
+    if not args.no_cpu:
+        base = cpu_baseline_c1(X, y, cfg, W.cpu().numpy()[:, 0])
+        log("oracle: %s" % base)
+    line = {"metric": "FP64 solve time, %d iterations, n=4096 d=8, 1 GPU" % T, "value": t_gpu,
+            "unit": "s", "n_gpus": 1, "steps": T, "warmup": 1, "ms_per_step": 1e3 * t_gpu / T,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic (X ~ N(0, I_8), y = sum_j sin(x_j) + N(0, 0.1^2))",
+            "config": {"workload": "c1_fp64_rbf_n4096_d8", "n": cfg["n"], "d": cfg["d"], "b": cfg["b"],
+                       "r": cfg["r"], "lambda": cfg["lam"], "rho": cfg["rho"], "iters": T},
+            "relres_gpu": relres_gpu, "roofline": None, "cpu_baseline": base}
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_c1(X, y, cfg, Wg):
+    """The oracle's full run and the direct solve of the small float64 workload, on the host
+    cores (BLAS threads), with the relative residuals and the GPU-oracle difference."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import adasap as OA
+    from oracle import kernels as OK
+    from oracle import linsys as OL
+
+    cores, nproc, ncpu, model = host_cores()
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        Wo, _ = OA.adasap(X, y, OK.RBF, cfg["ell"], cfg["lam"], cfg["b"], cfg["r"], cfg["iters"],
+                          cfg["seed"], rho_rule=1, rho=cfg["rho"])
+        t_or = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Wd = OL.direct_solve(X, y[:, None], OK.RBF, cfg["ell"], cfg["lam"])
+        t_dir = time.perf_counter() - t0
+        Y = y[:, None]
+        Wo = Wo.reshape(-1, 1)
+        delta = float(np.linalg.norm(OL.residual(X, np.zeros_like(Y), Wg[:, None] - Wo, OK.RBF,
+                                                 cfg["ell"], cfg["lam"])) / np.linalg.norm(Y))
+        rr_or = float(OL.relres(X, Y, Wo, OK.RBF, cfg["ell"], cfg["lam"])[0])
+        rr_dir = float(OL.relres(X, Y, Wd, OK.RBF, cfg["ell"], cfg["lam"])[0])
+    return {"value": t_or, "unit": "s", "cores": cores, "nproc": nproc, "logical_cpus": ncpu,
+            "cpu_model": model, "kind": "oracle",
+            "sample": "the whole workload: %d iterations" % cfg["iters"],
+            "relres_oracle": rr_or, "direct_solve_s": t_dir, "relres_direct": rr_dir,
+            "delta_gpu_vs_oracle": delta}
+
+
+def bench_batched_ttr(args, torch, binding, inputs):
+    """The 256 uneven problems to relative residual 1e-3: the fewest rounds (bisected between
+    powers of two) after which every problem of one batched solve is at or below 1e-3, against
+    a loop of single-problem solves that each stop at their first per-pass check <= 1e-3."""
+    w = inputs.WORKLOADS["c4_batched_256"]
+    ns, ds, ells = inputs.c4_problem_sizes(seed=w["seed"], count=w["count"], nmin=w["nmin"],
+                                           nmax=w["nmax"], dmin=w["dmin"], dmax=w["dmax"],
+                                           ellmin=w["ellmin"], ellmax=w["ellmax"])
+    b, r, lam = w["b"], w["r"], w["lam"]
+    lib = binding.load()
+    Xs, Ys, Ws = [], [], []
+    for p in range(len(ns)):
+        X, y = inputs.make_c4_problem(p, int(ns[p]), int(ds[p]), seed=w["seed"])
+        Xs.append(torch.as_tensor(X, dtype=torch.float32).cuda())
+        Ys.append(torch.as_tensor(y[:, None], dtype=torch.float32).cuda())
+        Ws.append(torch.zeros((int(ns[p]), 1), dtype=torch.float32, device="cuda"))
+
+    def batch(T):
+        cfg = lib.config(kernel="rbf", lam=lam, block_size=b, rank=r, max_iters=T, seed=w["seed"],
+                         precision="fp32", tol=1e-3)
+        for Wt in Ws:
+            Wt.zero_()
+        torch.cuda.synchronize()
+        reps = lib.solve_batch(cfg, Xs, Ys, Ws, ells)
+        worst = max(rp["relres"] for rp in reps)
+        log("batch T=%d: worst relres %.3e, %.3f s" % (T, worst, reps[0]["solve_ms"] / 1e3))
+        return worst, reps[0]["solve_ms"] / 1e3
+
+    lo, hi, T = 0, None, 8
+    while hi is None and T <= 8192:
+        worst, sec = batch(T)
+        if worst <= 1e-3:
+            hi, hi_sec = T, sec
+        else:
+            lo, T = T, 2 * T
+    if hi is not None:
+        while hi - lo > max(2, hi // 16):
+            mid = (lo + hi) // 2
+            worst, sec = batch(mid)
+            if worst <= 1e-3:
+                hi, hi_sec = mid, sec
+            else:
+                lo = mid
+    # the loop of single-problem solves, each stopping at its first per-pass check <= 1e-3
+    single_s, single_it, reached = 0.0, 0, 0
+    for p in range(len(ns)):
+        per_pass = int(math.ceil(ns[p] / b))
+        h = lib.create(lib.config(kernel="rbf", lengthscale=float(ells[p]), lam=lam, block_size=b,
+                                  rank=r, max_iters=per_pass * 400, tol=1e-3, check_every=per_pass,
+                                  seed=w["seed"] + p, precision="fp32"), Xs[p], Ys[p])
+        Wt = torch.zeros_like(Ys[p])
+        rp = h.solve(Wt)
+        h.close()
+        single_s += rp["solve_ms"] / 1e3
+        single_it += rp["iters"]
+        reached += int(0 <= rp["relres"] <= 1e-3)
+    log("loop of single solves: %.2f s, %d iterations, %d of %d reached" % (single_s, single_it,
+                                                                          reached, len(ns)))
+    line = {"metric": "time for 256 uneven problems to reach relres 1e-3 (s), batched vs loop, 1 GPU",
+            "value": None if hi is None else round(hi_sec, 3), "unit": "s", "n_gpus": 1,
+            "steps": hi, "warmup": 0, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 (f16 hi/lo matrix-core distances), f64 Nystrom cores",
+            "data": "synthetic (seeded Gaussian X, sum-of-sines targets)",
+            "config": {"workload": "batched_256_rbf_uneven_ttr", "problems": len(ns), "b": b, "r": r,
+                       "lambda": lam, "granularity_rounds": None if hi is None else hi - lo},
+            "batched": {"rounds": hi, "seconds": None if hi is None else round(hi_sec, 3)},
+            "single_loop": {"seconds": round(single_s, 3), "iterations": single_it,
+                            "reached": reached, "checked_every": "one data pass"},
+            "roofline": None, "cpu_baseline": None}
     print(json.dumps(line), flush=True)
 
 

@@ -1369,6 +1369,30 @@ __global__ __launch_bounds__(256) void fused_scale_kernel(int nwg, int k, const 
   }
 }
 
+// one element of the update: returns the new z; writes V, Z and W in place
+__device__ __forceinline__ float nest_elem(float* __restrict__ V, float* __restrict__ Z,
+                                           void* __restrict__ W, DT wt, int64_t g, double v,
+                                           double z, double st, bool hit, double beta,
+                                           double gamma, double alpha, double cz, int z_next,
+                                           int accel, float& vout) {
+  double vn = v, zn = z, w = z;
+  if (accel) {
+    vn = beta * v + (1.0 - beta) * z;
+    zn = alpha * (z_next ? vn : v) + (1.0 - alpha) * z;
+  }
+  if (hit) {
+    if (accel) vn -= gamma * st;
+    zn -= cz * st;
+    w -= st;
+  }
+  vout = (float)vn;
+  if (W) {
+    if (wt == DT::F64) static_cast<double*>(W)[g] = w;
+    else static_cast<float*>(W)[g] = (float)w;
+  }
+  return (float)zn;
+}
+
 template <bool WIDE>
 __global__ __launch_bounds__(256) void nesterov_pack_kernel(
     int64_t n, int k, int64_t ntiles, float* __restrict__ V, float* __restrict__ Z,
@@ -1383,8 +1407,61 @@ __global__ __launch_bounds__(256) void nesterov_pack_kernel(
   const double eta = sc->eta;
   const double cz = accel ? (z_next ? alpha * gamma + 1.0 - alpha : 1.0 - alpha) : 1.0;
   const int words = WIDE ? nq * 128 : nq * 64;  // half8 words of one packed tile
+  // k a multiple of 8: each thread takes 8 consecutive elements of one row per step (two
+  // 16-byte loads of V and of Z) and keeps the maxima of its columns in registers
+  const bool vec = (k % 8) == 0;
+  float rv[8] = {0, 0, 0, 0, 0, 0, 0, 0}, rz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int vcol = -1;  // first of the thread's 8 columns (fixed when 256 * 8 is a multiple of k)
   for (int64_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
     __syncthreads();  // the previous tile's packing has read zt
+    if (vec) {
+      for (int e0 = tid * 8; e0 < TILE * k; e0 += 256 * 8) {
+        const int r = e0 / k, c0 = e0 % k;
+        const int64_t i = T * TILE + r;
+        float zo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (i < n) {
+          const int64_t g = i * k + c0;
+          const float4 va = *reinterpret_cast<const float4*>(V + g);
+          const float4 vb = *reinterpret_cast<const float4*>(V + g + 4);
+          const float4 za = *reinterpret_cast<const float4*>(Z + g);
+          const float4 zb = *reinterpret_cast<const float4*>(Z + g + 4);
+          const float vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+          const float zz[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+          const int64_t p = pos[i];
+          const bool hit = (uint32_t)((uint64_t)p >> 32) == stamp;
+          const double* Drow = hit ? D + (int64_t)(p & 0xffffffffLL) * k + c0 : nullptr;
+          float vo[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const double st = hit ? eta * Drow[j] : 0.0;
+            zo[j] = nest_elem(V, Z, W, wt, g + j, (double)vv[j], (double)zz[j], st, hit, beta,
+                              gamma, alpha, cz, z_next, accel, vo[j]);
+          }
+          if (accel) {
+            *reinterpret_cast<float4*>(V + g) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+            *reinterpret_cast<float4*>(V + g + 4) = make_float4(vo[4], vo[5], vo[6], vo[7]);
+          }
+          *reinterpret_cast<float4*>(Z + g) = make_float4(zo[0], zo[1], zo[2], zo[3]);
+          *reinterpret_cast<float4*>(Z + g + 4) = make_float4(zo[4], zo[5], zo[6], zo[7]);
+          if ((256 * 8) % k == 0) {
+            vcol = c0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              rv[j] = fmaxf(rv[j], fabsf(accel ? vo[j] : zo[j]));
+              rz[j] = fmaxf(rz[j], fabsf(zo[j]));
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              atomicMax(&mv[c0 + j], __float_as_uint(fabsf(accel ? vo[j] : zo[j])));
+              atomicMax(&mz[c0 + j], __float_as_uint(fabsf(zo[j])));
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) zt[r * k + c0 + j] = zo[j];
+      }
+    } else {
     for (int e = tid; e < TILE * k; e += 256) {
       const int64_t i = T * TILE + e / k;
       const int c = e % k;
@@ -1418,6 +1495,7 @@ __global__ __launch_bounds__(256) void nesterov_pack_kernel(
       }
       zt[(e / k) * k + c] = zo;
     }
+    }
     __syncthreads();
     for (int e = tid; e < words; e += 256) {
       const int lane = e % 64;
@@ -1445,6 +1523,13 @@ __global__ __launch_bounds__(256) void nesterov_pack_kernel(
         }
         packed[(T * nq + q) * 64 + lane] = h;
       }
+    }
+  }
+  if (vcol >= 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      atomicMax(&mv[vcol + j], __float_as_uint(rv[j]));
+      atomicMax(&mz[vcol + j], __float_as_uint(rz[j]));
     }
   }
   __syncthreads();

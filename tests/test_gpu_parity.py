@@ -162,9 +162,10 @@ def test_solve_fp64_trajectory_parity(lib, case):
 
 
 def test_solve_small_fp64_workload(lib):
+    # the whole 200-iteration run of the small float64 workload
     cfg = inputs.WORKLOADS["c1_fp64_n4096"]
     X, y = inputs.make_c1(seed=cfg["seed"])
-    T = 40
+    T = cfg["iters"]
     Wo, info = OA.adasap(X, y, OK.RBF, cfg["ell"], cfg["lam"], cfg["b"], cfg["r"], T, cfg["seed"],
                          rho_rule=1, rho=cfg["rho"])
     Wg, rep, tr, h = _gpu_solve(lib, X, y[:, None], kernel="rbf", lengthscale=cfg["ell"],
