@@ -122,6 +122,9 @@ typedef struct {
   int64_t step1_launches;  /* number of those launches (batched solves: the rounds run eagerly) */
   int32_t jacobi_sweeps_max; /* most sweeps one Nystrom eigendecomposition needed */
   int32_t reserved;        /* batched solves: column tiles per work item chosen by the autotuner */
+  int32_t tuned_rows_per_wg; /* batched solves: rows of X_B per workgroup (128 or 256) chosen by the autotuner */
+  int32_t tuned_wg_per_cu;   /* batched solves: persistent workgroups per CU (2 or 4) chosen by the autotuner */
+  int32_t tuned_from_cache;  /* batched solves: 1 if the choice came from this process's tuning cache */
 } adasap_report_t;
 
 typedef struct adasap_handle_s* adasap_handle_t;
@@ -269,9 +272,12 @@ typedef struct {
  * for every problem.  When tol > 0 or check_every > 0 each problem's final relative residual
  * is computed.  `reports` (host, count entries, may be NULL) receives per-problem statistics.
  * Execution: the host draws round t + 1's blocks while the device runs round t; the first
- * round times the step-I launch for work items of 16, 32, 64 and 128 column tiles and keeps
- * the fastest; every round but the first and the last replays one captured hipGraph of the
- * round's device work (the iteration counter reaches it through device memory).
+ * round times the step-I launch for every tile shape (128 or 256 rows per workgroup), 2 or 4
+ * persistent workgroups per CU and work items of 16, 32, 64 or 128 column tiles, and keeps
+ * the fastest (a process-wide cache keyed by device, kernel, b and the problems' tile counts
+ * and dimensions skips the timing for a batch of the same shapes); every round but the first
+ * and the last replays one captured hipGraph of the round's device work (the iteration
+ * counter reaches it through device memory).
  * Synchronises the stream. */
 adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int32_t count,
                                    const adasap_config_t* cfg, int32_t dtype, void* stream,

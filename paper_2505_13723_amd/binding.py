@@ -66,6 +66,8 @@ class Report(ctypes.Structure):
         ("refine_done", ctypes.c_int32), ("not_pd_events", ctypes.c_int32), ("status", ctypes.c_int32),
         ("step1_kernel_ms", ctypes.c_double), ("step1_launches", ctypes.c_int64),
         ("jacobi_sweeps_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tuned_rows_per_wg", ctypes.c_int32), ("tuned_wg_per_cu", ctypes.c_int32),
+        ("tuned_from_cache", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -14,6 +14,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -50,6 +52,54 @@ __global__ void fill_row_prob_kernel(int64_t rows, int32_t* __restrict__ row_pro
                                      int64_t off) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < rows) row_prob[off + i] = p;
+}
+
+// step-I tile shapes chosen by the autotuner, kept for the life of the process per device and
+// batch shape (kernel, block size, and every problem's column-tile count and dimension)
+struct TuneKey {
+  int dev, kern;
+  int64_t b;
+  uint64_t shape;
+  bool operator<(const TuneKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (kern != o.kern) return kern < o.kern;
+    if (b != o.b) return b < o.b;
+    return shape < o.shape;
+  }
+};
+struct TuneVal {
+  int rt, wg_per_cu, chunk;
+};
+std::mutex tune_mu;
+std::map<TuneKey, TuneVal> tune_cache;
+
+TuneKey tune_key(int dev, const MfmaBatchPack& bp, int64_t b) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over (problems, tiles, d) of every problem
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)bp.P);
+  for (int p = 0; p < bp.P; ++p) {
+    mix((uint64_t)bp.ntiles[p]);
+    mix((uint64_t)bp.d[p]);
+  }
+  return TuneKey{dev, bp.kern, b, h};
+}
+
+bool tune_lookup(const TuneKey& k, TuneVal& v) {
+  std::lock_guard<std::mutex> g(tune_mu);
+  auto it = tune_cache.find(k);
+  if (it == tune_cache.end()) return false;
+  v = it->second;
+  return true;
+}
+
+void tune_store(const TuneKey& k, const TuneVal& v) {
+  std::lock_guard<std::mutex> g(tune_mu);
+  tune_cache[k] = v;
 }
 
 adasap_status_t invalid(const std::string& m) {
@@ -114,7 +164,7 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
   ADASAP_TRY(mfma_batch_pack_create(bp, P, n.data(), d.data(), Xp.data(), dt, ell.data(),
                                     cfg->kernel, s));
   MfmaQueue q;
-  ADASAP_TRY(mfma_batch_queue_create(bp, b, 64, q, s));
+  ADASAP_TRY(mfma_batch_queue_create(bp, b, 64, 4, q, s));
   const int64_t R = bp.rows_total;
   DevBuf V, Z, Wp, Yp, rowp, dcoef, Bdev, G, D, Om, Ysk, Mo, Qo, Rinv, Bm, H, ev, Vr, T, S, cinv,
       cisq, U, rot, vv, ww, uu, zz, coef, coef2, scb, colsB, pg, pg2, pd, res, colq, tmp;
@@ -250,7 +300,8 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
       if (*g) (void)hipGraphDestroy(*g);
     }
   } graphfree{&graph, &graph_exec};
-  int chosen_chunk = 64;
+  TuneVal chosen{4, 2, 64};
+  int tuned_from_cache = 0;
 
   // the device work of one round (B_t and t already uploaded); `last` also writes W
   auto round = [&](bool last, bool timed) -> adasap_status_t {
@@ -359,26 +410,41 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     ADASAP_HIP(hipEventRecord(slot_ev[slot], s));
     const bool last = t + 1 == Tmax;
     if (t == 0) {
-      // autotuner: time the step-I launch for a few work-item sizes on this batch, keep the fastest
-      const int cands[4] = {16, 32, 64, 128};
-      float best = 1e30f;
-      KbEpilogue none;
-      for (int ci = 0; ci < 4; ++ci) {
-        MfmaQueue qc;
-        ADASAP_TRY(mfma_batch_queue_create(bp, b, cands[ci], qc, s));
-        float ms = 0;
-        for (int rep = 0; rep < 2; ++rep) {  // the first launch warms caches and allocations
-          ADASAP_TRY(mfma_batch_stepI(bp, qc, Bdev.as<int64_t>(), b, Z.as<float>(), G.as<double>(),
-                                      none, w1, s, k0, k1));
-          ADASAP_HIP(hipEventSynchronize(k1));
-          ADASAP_HIP(hipEventElapsedTime(&ms, k0, k1));
-        }
-        if (ms < best) {
-          best = ms;
-          chosen_chunk = cands[ci];
-        }
+      // autotuner: the step-I launch's tile shape (rows per workgroup), workgroups per CU and
+      // work-item size, timed on this batch (second of two launches each) unless the process
+      // has tuned the same shapes on this device before
+      int dev = 0;
+      ADASAP_HIP(hipGetDevice(&dev));
+      const TuneKey key = tune_key(dev, bp, b);
+      TuneVal tv;
+      if (tune_lookup(key, tv)) {
+        tuned_from_cache = 1;
+      } else {
+        float best = 1e30f;
+        KbEpilogue none;
+        for (int rt : {2, 4})
+          for (int wgcu : {2, 4})
+            for (int chunk : {16, 32, 64, 128}) {
+              MfmaQueue qc;
+              qc.wg_per_cu = wgcu;
+              ADASAP_TRY(mfma_batch_queue_create(bp, b, chunk, rt, qc, s));
+              float ms = 0;
+              for (int rep = 0; rep < 2; ++rep) {  // the first launch warms caches and allocations
+                ADASAP_TRY(mfma_batch_stepI(bp, qc, Bdev.as<int64_t>(), b, Z.as<float>(),
+                                            G.as<double>(), none, w1, s, k0, k1));
+                ADASAP_HIP(hipEventSynchronize(k1));
+                ADASAP_HIP(hipEventElapsedTime(&ms, k0, k1));
+              }
+              if (ms < best) {
+                best = ms;
+                tv = TuneVal{rt, wgcu, chunk};
+              }
+            }
+        tune_store(key, tv);
       }
-      if (chosen_chunk != 64) ADASAP_TRY(mfma_batch_queue_create(bp, b, chosen_chunk, q, s));
+      chosen = tv;
+      q.wg_per_cu = tv.wg_per_cu;
+      if (tv.rt != 4 || tv.chunk != 64) ADASAP_TRY(mfma_batch_queue_create(bp, b, tv.chunk, tv.rt, q, s));
     }
     if (t >= 1 && !last && use_graph) {
       if (!graph_exec) {
@@ -427,7 +493,10 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     rep.solve_ms = solve_ms;
     rep.step1_kernel_ms = step1_ms;
     rep.step1_launches = step1_timed;
-    rep.reserved = chosen_chunk;
+    rep.reserved = chosen.chunk;
+    rep.tuned_rows_per_wg = 64 * chosen.rt;
+    rep.tuned_wg_per_cu = chosen.wg_per_cu;
+    rep.tuned_from_cache = tuned_from_cache;
     rep.eta_last = hs[p].eta;
     rep.rho_last = hs[p].rho;
     rep.lambda_hat_last = hs[p].lam_hat;

@@ -108,6 +108,8 @@ struct MfmaBatchPack {
 struct MfmaQueue {
   int nitems = 0;
   int rows_per_wg = 256;
+  int rt = 4;         // row tiles of 16 per wave: 64 rt rows per workgroup (2 or 4)
+  int wg_per_cu = 2;  // persistent workgroups per CU (2 or 4)
   DevBuf items, item_start, nchunk, counter;
 };
 
@@ -123,7 +125,7 @@ adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t*
                                          double* out, const KbEpilogue& ep, MfmaWork& w,
                                          hipStream_t s);
 adasap_status_t mfma_batch_queue_create(const MfmaBatchPack& bp, int64_t b, int64_t chunk_tiles,
-                                        MfmaQueue& q, hipStream_t s);
+                                        int rt, MfmaQueue& q, hipStream_t s);
 // G[p] = K(X_B[p], X[p]) Z[p] + epilogue for all problems in one persistent launch
 // (Z: float32 on the global padded rows, k = 1)
 adasap_status_t mfma_batch_stepI(const MfmaBatchPack& bp, MfmaQueue& q, const int64_t* B, int64_t b,

@@ -1866,10 +1866,26 @@ adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t*
   return ADASAP_OK;
 }
 
+template <int RT>
+static adasap_status_t mkq_launch(int kern, int grid, const MkArgs& a, hipStream_t s) {
+  switch (kern) {
+    case ADASAP_RBF: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_RBF, MODE_F32V, 1, RT>), dim3(grid), dim3(256), 0, s, a); break;
+    case ADASAP_MATERN12: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN12, MODE_F32V, 1, RT>), dim3(grid), dim3(256), 0, s, a); break;
+    case ADASAP_MATERN32: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN32, MODE_F32V, 1, RT>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN52, MODE_F32V, 1, RT>), dim3(grid), dim3(256), 0, s, a); break;
+  }
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
+}
+
 adasap_status_t mfma_batch_queue_create(const MfmaBatchPack& bp, int64_t b, int64_t chunk_tiles,
-                                        MfmaQueue& q, hipStream_t s) {
+                                        int rt, MfmaQueue& q, hipStream_t s) {
+  if (rt != 2 && rt != 4) {
+    set_error("batched step I: row tiles per wave must be 2 or 4");
+    return ADASAP_ERR_INVALID_ARG;
+  }
   const int P = bp.P;
-  const int rows_per_wg = WAVES * 4 * 16;
+  const int rows_per_wg = WAVES * rt * 16;
   const int rwg = (int)((b + rows_per_wg - 1) / rows_per_wg);
   std::vector<MkItem> items;
   std::vector<int64_t> start(P);
@@ -1891,6 +1907,7 @@ adasap_status_t mfma_batch_queue_create(const MfmaBatchPack& bp, int64_t b, int6
   }
   q.nitems = (int)items.size();
   q.rows_per_wg = rows_per_wg;
+  q.rt = rt;
   ADASAP_TRY(q.items.ensure(items.size() * sizeof(MkItem)));
   ADASAP_TRY(q.item_start.ensure((size_t)P * sizeof(int64_t)));
   ADASAP_TRY(q.nchunk.ensure((size_t)P * sizeof(int)));
@@ -1928,15 +1945,12 @@ adasap_status_t mfma_batch_stepI(const MfmaBatchPack& bp, MfmaQueue& q, const in
   int dev = 0, cus = 256;
   ADASAP_HIP(hipGetDevice(&dev));
   ADASAP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int grid = cus * 2;  // two workgroups per CU, each drains the queue
+  // persistent workgroups (two or four per CU, within the launch bounds of four), each
+  // draining the queue
+  const int grid = cus * (q.wg_per_cu == 4 ? 4 : 2);
   if (ev0) ADASAP_HIP(hipEventRecord(ev0, s));
-  switch (bp.kern) {
-    case ADASAP_RBF: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_RBF, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    case ADASAP_MATERN12: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN12, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    case ADASAP_MATERN32: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN32, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((mkq_kernel<2, ADASAP_MATERN52, MODE_F32V, 1, 4>), dim3(grid), dim3(256), 0, s, a); break;
-  }
-  ADASAP_LAUNCH_CHECK();
+  if (q.rt == 2) ADASAP_TRY(mkq_launch<2>(bp.kern, grid, a, s));
+  else ADASAP_TRY(mkq_launch<4>(bp.kern, grid, a, s));
   if (ev1) ADASAP_HIP(hipEventRecord(ev1, s));
   hipLaunchKernelGGL(mkq_reduce_kernel, dim3((unsigned)((b + 255) / 256), bp.P), dim3(256), 0, s,
                      w.part.as<float>(), q.item_start.as<int64_t>(), q.nchunk.as<int>(), b, 1,

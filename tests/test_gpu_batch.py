@@ -104,3 +104,27 @@ def test_batch_of_32_benchmark_problems_matches_oracle(lib):
         worst = max(worst, d)
         assert d <= 1e-3, (int(p), int(ns[p]), int(ds[p]), d)
     print("32 batched problems: worst delta %.3e" % worst, flush=True)
+
+
+def test_autotuner_choice_is_cached_and_reproducible(lib):
+    # the first batch of these shapes times every tile shape; a second batch of the same shapes
+    # takes the cached choice and, with the same seed, reproduces the first result bit for bit
+    Xs, Ys = _problems()
+    cfg = lib.config(kernel="rbf", lam=2e-2, block_size=256, rank=32, max_iters=6, seed=91,
+                     precision="fp32")
+    Xd = [torch.as_tensor(X, dtype=torch.float32).cuda() for X in Xs]
+    Yd = [torch.as_tensor(y, dtype=torch.float32).cuda() for y in Ys]
+    ells = [s[2] for s in SIZES]
+    runs = []
+    for _ in range(2):
+        Wd = [torch.zeros_like(y) for y in Yd]
+        reps = lib.solve_batch(cfg, Xd, Yd, Wd, ells)
+        runs.append(([W.cpu() for W in Wd], reps[0]))
+    (W1, r1), (W2, r2) = runs
+    assert r1["tuned_rows_per_wg"] in (128, 256) and r1["tuned_wg_per_cu"] in (2, 4)
+    assert r1["reserved"] in (16, 32, 64, 128)
+    assert r2["tuned_from_cache"] == 1
+    assert (r2["tuned_rows_per_wg"], r2["tuned_wg_per_cu"], r2["reserved"]) == \
+        (r1["tuned_rows_per_wg"], r1["tuned_wg_per_cu"], r1["reserved"])
+    for a, b in zip(W1, W2):
+        assert torch.equal(a, b)
