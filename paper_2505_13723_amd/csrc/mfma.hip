@@ -373,8 +373,12 @@ __device__ inline float kval(float s, float p) {
   if constexpr (KERN == ADASAP_RBF) {
     return __builtin_amdgcn_exp2f(s);
   } else {
-    const float t = s < 0.0f ? -s : 0.0f;  // (r/ell)^2
-    const float a = __builtin_sqrtf(t) * p;   // p = 1, sqrt(3) or sqrt(5)
+    // a = p r / ell from s = -(r/ell)^2: the hardware square root (one instruction, within
+    // 1 ulp) of |s| (a free source modifier).  The correctly rounded sqrtf and a clamp at
+    // zero expand to about a dozen vector instructions, which made the Matern products
+    // issue-bound on the vector ALUs.  s > 0 only where rounding of the split distance left
+    // r^2 slightly negative; |s| is then within that rounding error of r^2.
+    const float a = __builtin_amdgcn_sqrtf(__builtin_fabsf(s)) * p;  // p = 1, sqrt(3) or sqrt(5)
     const float e = __builtin_amdgcn_exp2f(-a * 1.4426950408889634f);
     if constexpr (KERN == ADASAP_MATERN12) return e;
     else if constexpr (KERN == ADASAP_MATERN32) return (1.0f + a) * e;
