@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--bo-acq", type=int, default=1000, help="acquisitions per BO step")
     ap.add_argument("--bo-seeds", type=int, default=1, help="objective functions per lengthscale")
     ap.add_argument("--bo-passes", type=int, default=10, help="ADASAP data passes per solve")
+    ap.add_argument("--bo-ells", default="2,3", help="lengthscales of the BO objectives")
     ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default=None,
                     help="precision of the single-problem workloads (default: the workload's)")
     ap.add_argument("--check-rows", type=int, default=0,
@@ -597,7 +598,7 @@ def bench_bo(args, torch, binding):
     lib = binding.load()
     res = {}
     t0 = time.perf_counter()
-    for ell in (2.0, 3.0):
+    for ell in [float(v) for v in args.bo_ells.split(",")]:
         runs = []
         for sd in range(args.bo_seeds):
             out = bo.thompson_bo(lib, d=8, ell=ell, noise=1e-6, n0=args.bo_n0, steps=args.bo_steps,
