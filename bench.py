@@ -215,9 +215,28 @@ def main():
                      "kernel": "mkw_kernel (Step-I kernel-block product, float16 32x32x16 MFMA)",
                      "kernel_ms": round(kern_ms, 4),
                      "algorithmic_flops_per_launch": flops_step1},
+        # the same launch against the instruction rates of this part, measured in the same
+        # run (adasap_probe_rates): the 32x32x16 float16 MFMA on the flops per pair the kernel
+        # executes (48 distance slots for the 3d + 6 = 39 of the hi/lo split, and K Z), one
+        # v_exp_f32 and half a conversion per pair on the vector ALUs
+        "roofline_probe": probe_bound(lib.probe_rates(), b, n, d, k, kern_ms),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def probe_bound(rates, b, n, d, k, kern_ms, simds=1024):
+    """T_bound = max(MFMA time, vector time) of the MIXED Step-I launch at the measured rates."""
+    pairs = float(b) * n
+    slots = 16 * math.ceil((3 * d + 6) / 16)
+    mfma_ms = pairs * 2 * (slots + k) / (rates["mfma32_f16_tflops"] * 1e12) * 1e3
+    valu_ms = pairs / 64 * (rates["exp_ns"] + 0.5 * rates["valu_ns"]) / simds * 1e-6
+    bound = max(mfma_ms, valu_ms)
+    return {"t_bound_ms": round(bound, 4), "mfma_ms": round(mfma_ms, 4), "valu_ms": round(valu_ms, 4),
+            "measured_ms": round(kern_ms, 4), "frac": round(bound / kern_ms, 4) if kern_ms > 0 else None,
+            "rates": {key: round(v, 4) for key, v in rates.items()},
+            "basis": "rates of this part from adasap_probe_rates in the same run; under the Step-I "
+                     "load the part runs power-limited at 1.8-1.9 GHz (GRBM_GUI_ACTIVE)"}
 
 
 CERT_ROWS = 1 << 17

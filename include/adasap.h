@@ -321,6 +321,15 @@ adasap_status_t adasap_kblock_matmul_noalloc(int32_t kernel, double lengthscale,
                                              const void* Xr, const void* Xc, const void* R,
                                              void* out, int32_t dtype, void* stream);
 
+/* Instruction rates of the current device, for the rooflines of a measurement (not a step
+ * of the method): register-only loops of v_exp_f32, of v_fma_f32 and of float16 32x32x16
+ * MFMAs (four independent accumulators per wave) over 2048 workgroups of 256 threads,
+ * one warm-up and one timed launch each (about 30 ms in all).  out (host, 3 doubles):
+ * [0] ns per v_exp_f32 wave instruction per SIMD, [1] ns per v_fma_f32 wave instruction
+ * per SIMD, [2] TFLOP/s of the 32x32x16 MFMAs over the device.  Allocates a 2 MiB
+ * scratch buffer; synchronises the stream. */
+adasap_status_t adasap_probe_rates(void* stream, double* out);
+
 /* Randomized Nystrom factors of a b x b PSD matrix from its sketch (Appendix,
  * Alg. NysApprox): Ysk = M Omega and Omega (device, b x r, float64).  Outputs
  * (device, float64): U (b x r, orthonormal columns), S (r, descending, >= 0) and

@@ -95,6 +95,7 @@ _SIGNATURES = {
     "adasap_predict": (_I32, [_P, _P, _I64, _P, _P]),
     "adasap_posterior_samples": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "adasap_column_argmax": (_I32, [_I64, _I32, _I64, _P, _I32, _P, _P]),
+    "adasap_probe_rates": (_I32, [_P, ctypes.POINTER(ctypes.c_double)]),
     "adasap_predictive_metrics": (_I32, [_I64, _I32, _P, _P, _D, _I32, _P, ctypes.POINTER(_D),
                                          ctypes.POINTER(_D)]),
     "adasap_residual": (_I32, [_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
@@ -300,6 +301,13 @@ class Library:
         self.check(self.cdll.adasap_column_argmax(a.shape[0], a.shape[1], a.stride(0), _ptr(a),
                                                   _dtype_code(a), _stream(), _ptr(out)))
         return out
+
+    def probe_rates(self):
+        """Measured instruction rates of the device: ns per v_exp_f32 and per v_fma_f32 wave
+        instruction per SIMD, and TFLOP/s of float16 32x32x16 MFMAs."""
+        out = (ctypes.c_double * 3)()
+        self.check(self.cdll.adasap_probe_rates(_stream(), out))
+        return {"exp_ns": out[0], "valu_ns": out[1], "mfma32_f16_tflops": out[2]}
 
     def nystrom(self, Ysk, Omega, eps):
         torch = _torch()

@@ -20,7 +20,9 @@
 //   MODE_F16   K and R in float16, one MFMA per (row tile, 16 right-hand sides); with 17 to
 //              64 right-hand sides the same product runs on 32x32x16 MFMAs (MODE_F16W, below)
 //   MODE_F16X3 K = K_hi + K_lo and R = R_hi + R_lo, three MFMAs (hi.hi + lo.hi + hi.lo)
-//   MODE_F32V  K in float32 times float32 R on the vector ALUs (k <= 4)
+//   MODE_F32V  K in float32 times float32 R on the vector ALUs (k <= 4); single and batched
+//              products take the distances on 32x32x16 MFMAs (mkv_kernel, below), the
+//              persistent batched Step I on the 16x16x32 form
 // The column range is split over workgroups; partial sums are added in a fixed order.
 #include <cmath>
 #include <type_traits>
@@ -987,6 +989,190 @@ __global__ __launch_bounds__(256, 2) void mkw_kernel(MkArgs a) {
       a.part + prob * a.bs_part + (int64_t)split * a.m * a.k);
 }
 
+// Wide tiles for the float32 vector mode (MODE_F32V, one to four right-hand sides): the
+// distances on 32x32x16 MFMAs as in the wide float16 form (NS K-slices of 16 of the packed
+// slots, 3d + 6 <= 48 for d <= 14, against 64 slots in two K-steps of the 16x16x32 form),
+// the kernel values and K Z in float32 on the vector ALUs.  A wave takes two row tiles of 32
+// (64 rows); lane l holds row l % 32 of each and the 16 columns 8 (r / 4) + 4 g + r % 4 of
+// the tile (g = l / 32), whose right-hand-side values it reads as four runs of four columns.
+// The two halves of a row's columns are added across lanes 32 apart after the last tile.
+template <int KS, int NS, int KERN, int KC>
+__device__ void mkv_tiles(const MkArgs& a, char* lds, const half8* colA_p, const void* rhs_p,
+                          const int64_t* ridx, int rw, int64_t T0, int64_t T1, float* out) {
+  constexpr int A_FR = 2 * KS * 64, R_W = (TILE * KC * 4) / 16, TOTAL16 = A_FR + R_W;
+  constexpr int BUF_BYTES = ((TOTAL16 + 255) / 256) * 256 * 16;
+  constexpr int LOADS16 = (TOTAL16 + 255) / 256;
+  static_assert(NS >= 1 && NS <= 2 * KS, "K-slices within the packed slots");
+  static_assert(LOADS16 <= 5, "tile loads per thread");
+  const int tid = threadIdx.x;
+  const int lane = tid % 64;
+  const int wave = tid / 64;
+  const int g = lane / 32;
+  const int64_t row_base = ((int64_t)rw * WAVES + wave) * 64;
+  half8 Bfr[2][NS];
+  static_for<2>([&](auto rc) {
+    constexpr int rt = decltype(rc)::value;
+    const int64_t row = row_base + rt * 32 + lane % 32;
+    const int64_t pt = row < a.m ? (ridx ? ridx[row] : row) : (ridx ? ridx[0] : 0);
+    static_for<NS>([&](auto sc) {
+      constexpr int sl = decltype(sc)::value;
+      Bfr[rt][sl] = a.rowv[pt * 8 + 2 * sl + g];
+    });
+  });
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) asm volatile("" ::"v"(Bfr[rt][sl]));
+  int aidx[NS];
+  {
+    const int c = lane % 32;
+    static_for<NS>([&](auto sc) {
+      constexpr int sl = decltype(sc)::value;
+      const int hb = 2 * sl + g;
+      aidx[sl] = ((c / 16) * KS + hb / 4) * 64 + (hb % 4) * 16 + c % 16;
+    });
+  }
+  float acc[2][KC];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[rt][c] = 0.0f;
+
+  struct Stage {
+    uint4 w0, w1, w2, w3, w4;
+  };
+  auto word = [](Stage& st, auto uc) __attribute__((always_inline)) -> uint4& {
+    constexpr int u = decltype(uc)::value;
+    if constexpr (u == 0) return st.w0;
+    else if constexpr (u == 1) return st.w1;
+    else if constexpr (u == 2) return st.w2;
+    else if constexpr (u == 3) return st.w3;
+    else return st.w4;
+  };
+  auto gload = [&](int64_t T) __attribute__((always_inline)) -> Stage {
+    Stage st;
+    const uint4* ca = reinterpret_cast<const uint4*>(colA_p) + T * A_FR;
+    const uint4* rb = reinterpret_cast<const uint4*>(rhs_p) + T * R_W;
+    static_for<LOADS16>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const int e = tid + u * 256;
+      const uint4* src = e < A_FR ? ca + e : (e < TOTAL16 ? rb + (e - A_FR) : ca);
+      word(st, uc) = *src;
+    });
+    return st;
+  };
+  auto sstore = [&](Stage st, int buf) __attribute__((always_inline)) {
+    uint4* dst = reinterpret_cast<uint4*>(lds + buf * BUF_BYTES);
+    static_for<LOADS16>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      dst[tid + u * 256] = word(st, uc);
+    });
+  };
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
+    const float* zr = reinterpret_cast<const float*>(Af + A_FR);
+    half8 A[NS];
+    static_for<NS>([&](auto sc) {
+      constexpr int sl = decltype(sc)::value;
+      A[sl] = Af[aidx[sl]];
+    });
+    // right-hand-side values of this lane's 16 columns: zc[r][c] for column 8 (r / 4) + 4 g + r % 4
+    float zc[16][KC];
+    static_for<4>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      const float4* zp = reinterpret_cast<const float4*>(zr + (8 * q + 4 * g) * KC);
+      static_for<KC>([&](auto wc) {
+        constexpr int w = decltype(wc)::value;
+        const float4 v = zp[w];
+        const float f[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int flat = 4 * w + e;  // (column within the run) * KC + right-hand side
+          zc[4 * q + flat / KC][flat % KC] = f[e];
+        }
+      });
+    });
+    // both row tiles' distances first, so that row tile 1's MFMAs run beside row tile 0's
+    // kernel values; all 16 values of a row tile before their products (independent chains)
+    f16v D[2];
+    static_for<2>([&](auto rc) {
+      constexpr int rt = decltype(rc)::value;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) D[rt][r] = 0.0f;
+      static_for<NS>([&](auto sc) {
+        constexpr int sl = decltype(sc)::value;
+        D[rt] = mfma32(A[sl], Bfr[rt][sl], D[rt]);
+      });
+    });
+    static_for<2>([&](auto rc) {
+      constexpr int rt = decltype(rc)::value;
+      float kv[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) kv[r] = kval<KERN>(D[rt][r], a.p);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+#pragma unroll
+        for (int c = 0; c < KC; ++c) acc[rt][c] = __builtin_fmaf(kv[r], zc[r][c], acc[rt][c]);
+    });
+  };
+
+  if (T0 < T1) {
+    auto tc = [&](int64_t T) { return T < T1 ? T : T1 - 1; };
+    Stage s0 = gload(T0);
+    sstore(s0, 0);
+    Stage s1 = gload(tc(T0 + 1));
+    __syncthreads();
+    int64_t T = T0;
+    for (; T + 1 < T1; T += 2) {
+      s0 = gload(tc(T + 2));
+      asm volatile("" ::: "memory");
+      compute(0);
+      sstore(s1, 1);
+      __syncthreads();
+      s1 = gload(tc(T + 3));
+      asm volatile("" ::: "memory");
+      compute(1);
+      sstore(s0, 0);
+      __syncthreads();
+    }
+    if (T < T1) compute(0);
+  }
+  static_for<2>([&](auto rc) {
+    constexpr int rt = decltype(rc)::value;
+    const int64_t row = row_base + rt * 32 + lane % 32;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const float v = acc[rt][c] + __shfl_xor(acc[rt][c], 32);
+      if (g == 0 && row < a.m && c < a.k) out[row * a.k + c] = v;
+    }
+  });
+}
+
+template <int KS, int NS, int KERN, int KC>
+__global__ __launch_bounds__(256, 4) void mkv_kernel(MkArgs a) {
+  constexpr int TOTAL16 = 2 * KS * 64 + (TILE * KC * 4) / 16;
+  __shared__ __attribute__((aligned(16))) char lds[2 * ((TOTAL16 + 255) / 256) * 256 * 16];
+  const int bid = blockIdx.x;
+  const int prob = blockIdx.y;
+  int split, rw;
+  if (a.xcd_map) {
+    const int per = (int)gridDim.x / 8;
+    const int item = (bid % 8) * per + bid / 8;
+    split = item / a.rwg;
+    rw = item % a.rwg;
+  } else {
+    split = bid / a.rwg;
+    rw = bid % a.rwg;
+  }
+  const int64_t T0 = (int64_t)split * a.tiles_per_split;
+  int64_t T1 = T0 + a.tiles_per_split;
+  if (T1 > a.ntiles) T1 = a.ntiles;
+  mkv_tiles<KS, NS, KERN, KC>(
+      a, lds, a.colA + prob * a.bs_colA, static_cast<const char*>(a.rhs) + prob * a.bs_rhs,
+      a.ridx ? a.ridx + prob * a.bs_ridx : nullptr, rw, T0, T1,
+      a.part + prob * a.bs_part + (int64_t)split * a.m * a.k);
+}
+
 // Persistent work-queue form for a batch of problems with uneven column counts: each
 // workgroup takes (problem, row workgroup, tile range) items from a global counter until the
 // table is exhausted; item i writes its partial sums to part[i][rows of its workgroup][k].
@@ -1050,22 +1236,16 @@ void launch_mk(const MkArgs& a, int grid, hipStream_t s) {
 
 template <int KS, int KERN, int MODE>
 adasap_status_t disp_nq(const MkArgs& a, int nq, int grid, hipStream_t s) {
-  if constexpr (MODE == MODE_F32V) {
-    if (nq == 1) launch_mk<KS, KERN, MODE, 1, 4>(a, grid, s);
-    else if (nq == 2) launch_mk<KS, KERN, MODE, 2, 4>(a, grid, s);
-    else launch_mk<KS, KERN, MODE, 4, 4>(a, grid, s);
-  } else {
-    constexpr int R4 = rt_of(MODE, 4);
-    switch (nq) {
-      case 1: launch_mk<KS, KERN, MODE, 1, R4>(a, grid, s); break;
-      case 2: launch_mk<KS, KERN, MODE, 2, R4>(a, grid, s); break;
-      case 3: launch_mk<KS, KERN, MODE, 3, R4>(a, grid, s); break;
-      case 4: launch_mk<KS, KERN, MODE, 4, R4>(a, grid, s); break;
-      case 5: launch_mk<KS, KERN, MODE, 5, 2>(a, grid, s); break;
-      case 6: launch_mk<KS, KERN, MODE, 6, 2>(a, grid, s); break;
-      case 7: launch_mk<KS, KERN, MODE, 7, 2>(a, grid, s); break;
-      default: launch_mk<KS, KERN, MODE, 8, 2>(a, grid, s); break;
-    }
+  constexpr int R4 = rt_of(MODE, 4);
+  switch (nq) {
+    case 1: launch_mk<KS, KERN, MODE, 1, R4>(a, grid, s); break;
+    case 2: launch_mk<KS, KERN, MODE, 2, R4>(a, grid, s); break;
+    case 3: launch_mk<KS, KERN, MODE, 3, R4>(a, grid, s); break;
+    case 4: launch_mk<KS, KERN, MODE, 4, R4>(a, grid, s); break;
+    case 5: launch_mk<KS, KERN, MODE, 5, 2>(a, grid, s); break;
+    case 6: launch_mk<KS, KERN, MODE, 6, 2>(a, grid, s); break;
+    case 7: launch_mk<KS, KERN, MODE, 7, 2>(a, grid, s); break;
+    default: launch_mk<KS, KERN, MODE, 8, 2>(a, grid, s); break;
   }
   return ADASAP_OK;
 }
@@ -1074,7 +1254,8 @@ template <int KS, int KERN>
 adasap_status_t disp_mode(const MkArgs& a, int mode, int nq, int grid, hipStream_t s) {
   if (mode == MODE_F16) return disp_nq<KS, KERN, MODE_F16>(a, nq, grid, s);
   if (mode == MODE_F16X3) return disp_nq<KS, KERN, MODE_F16X3>(a, nq, grid, s);
-  return disp_nq<KS, KERN, MODE_F32V>(a, nq, grid, s);
+  set_error("internal: the float32 vector mode runs the wide-tile kernel");
+  return ADASAP_ERR_INVALID_ARG;
 }
 
 template <int KS>
@@ -1094,11 +1275,7 @@ void launch_mk_grid(const MkArgs& a, dim3 grid, hipStream_t s) {
 
 template <int KS, int KERN>
 void disp_mode_grid(const MkArgs& a, int mode, int nq, dim3 grid, hipStream_t s) {
-  if (mode == MODE_F32V) {
-    if (nq == 1) launch_mk_grid<KS, KERN, MODE_F32V, 1, 4>(a, grid, s);
-    else if (nq == 2) launch_mk_grid<KS, KERN, MODE_F32V, 2, 4>(a, grid, s);
-    else launch_mk_grid<KS, KERN, MODE_F32V, 4, 4>(a, grid, s);
-  } else if (mode == MODE_F16X3) {
+  if (mode == MODE_F16X3) {
     switch (nq) {
       case 1: launch_mk_grid<KS, KERN, MODE_F16X3, 1, 4>(a, grid, s); break;
       case 2: launch_mk_grid<KS, KERN, MODE_F16X3, 2, 4>(a, grid, s); break;
@@ -1133,6 +1310,31 @@ adasap_status_t disp_wide(const MkArgs& a, int ks, int ns, int kern, int nqw, in
   if (ks == 1) launch_wide_kern<1, 2>(a, kern, nqw, grid, s);
   else if (ns == 3) launch_wide_kern<2, 3>(a, kern, nqw, grid, s);
   else launch_wide_kern<2, 4>(a, kern, nqw, grid, s);
+  return ADASAP_OK;
+}
+
+template <int KS, int NS, int KERN>
+void launch_vwide(const MkArgs& a, int kc, dim3 grid, hipStream_t s) {
+  if (kc == 1) hipLaunchKernelGGL((mkv_kernel<KS, NS, KERN, 1>), grid, dim3(256), 0, s, a);
+  else if (kc == 2) hipLaunchKernelGGL((mkv_kernel<KS, NS, KERN, 2>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((mkv_kernel<KS, NS, KERN, 4>), grid, dim3(256), 0, s, a);
+}
+
+template <int KS, int NS>
+void launch_vwide_kern(const MkArgs& a, int kern, int kc, dim3 grid, hipStream_t s) {
+  switch (kern) {
+    case ADASAP_RBF: launch_vwide<KS, NS, ADASAP_RBF>(a, kc, grid, s); break;
+    case ADASAP_MATERN12: launch_vwide<KS, NS, ADASAP_MATERN12>(a, kc, grid, s); break;
+    case ADASAP_MATERN32: launch_vwide<KS, NS, ADASAP_MATERN32>(a, kc, grid, s); break;
+    default: launch_vwide<KS, NS, ADASAP_MATERN52>(a, kc, grid, s); break;
+  }
+}
+
+adasap_status_t disp_vwide(const MkArgs& a, int ks, int ns, int kern, int kc, dim3 grid,
+                           hipStream_t s) {
+  if (ks == 1) launch_vwide_kern<1, 2>(a, kern, kc, grid, s);
+  else if (ns == 3) launch_vwide_kern<2, 3>(a, kern, kc, grid, s);
+  else launch_vwide_kern<2, 4>(a, kern, kc, grid, s);
   return ADASAP_OK;
 }
 
@@ -1214,6 +1416,9 @@ adasap_status_t mk_run(const half8* colA, int64_t ntiles, const half8* rowv,
     // K-slices of 16 for the 3d + 6 distance slots: 2 (d <= 8), 3 (d <= 14) or 4
     const int ns = KS == 1 ? 2 : (3 * d + 6 <= 48 ? 3 : 4);
     ADASAP_TRY(disp_wide(a, KS, ns, kern, rd.nq, grid, s));
+  } else if (rd.mode == MODE_F32V) {
+    const int ns = KS == 1 ? 2 : (3 * d + 6 <= 48 ? 3 : 4);
+    ADASAP_TRY(disp_vwide(a, KS, ns, kern, rd.nq, dim3(grid), s));
   } else if (KS == 1) {
     ADASAP_TRY(disp_kern<1>(a, kern, rd.mode, rd.nq, grid, s));
   } else {
@@ -1857,7 +2062,10 @@ adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t*
   else a.bs_rhs = nt * rd.nq * (mode == MODE_F16X3 ? 2 : 1) * 64 * 16;
   a.bs_part = (int64_t)splits * b * k;
   const dim3 grid(rwg * splits, P);
-  switch (bp.kern) {
+  if (mode == MODE_F32V) {
+    // every problem has two K-steps (d <= 16): all four 16-slot K-slices
+    ADASAP_TRY(disp_vwide(a, 2, 4, bp.kern, rd.nq, grid, s));
+  } else switch (bp.kern) {
     case ADASAP_RBF: disp_mode_grid<2, ADASAP_RBF>(a, rd.mode, rd.nq, grid, s); break;
     case ADASAP_MATERN12: disp_mode_grid<2, ADASAP_MATERN12>(a, rd.mode, rd.nq, grid, s); break;
     case ADASAP_MATERN32: disp_mode_grid<2, ADASAP_MATERN32>(a, rd.mode, rd.nq, grid, s); break;

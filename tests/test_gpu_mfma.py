@@ -111,3 +111,12 @@ def test_refinement_sweep_reduces_residual(lib):
     assert r0 > 1e-6, r0          # the float16 floor
     assert r1 < 1e-2 * r0, (r1, r0)
     assert rep1["relres"] == pytest.approx(r1, rel=1e-2, abs=1e-9)
+
+
+def test_probe_rates_are_plausible(lib):
+    # the instruction-rate probe behind the bench line's second roofline: a transcendental
+    # costs at least as much as a full-rate vector instruction, and the matrix cores reach a
+    # sizeable share of the part's published float16 rate (2.5 PFLOP/s at 2.4 GHz)
+    r = lib.probe_rates()
+    assert 0.5 < r["valu_ns"] < 20 and r["valu_ns"] <= r["exp_ns"] < 40, r
+    assert 500 < r["mfma32_f16_tflops"] < 2600, r
