@@ -715,7 +715,7 @@ __global__ __launch_bounds__(256, (mk_occupancy<KERN, MODE, NQ>())) void mk_kern
 // m + 32 (k / 8), element k % 8) and the row fragments from the row vectors.  The K Z products
 // are software-pipelined by one tile as in the 16x16 form; each accumulator adds the tiles
 // in order.
-template <int KS, int NS, int KERN, int NQW, bool DEFER>
+template <int KS, int NS, int KERN, int NQW>
 __device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const void* rhs_p,
                           const int64_t* ridx, int rw, int64_t T0, int64_t T1, float* out) {
   constexpr int A_FR = 2 * KS * 64, R_FR = NQW * 2 * 64, TOTAL16 = A_FR + R_FR;
@@ -813,16 +813,14 @@ __device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const
     });
   };
   auto kz_deferred = [&]() __attribute__((always_inline)) {
-    if constexpr (DEFER) {
-      static_for<2>([&](auto rc) {
-        constexpr int rt = decltype(rc)::value;
-        static_for<NQW>([&](auto qc) {
-          constexpr int q = decltype(qc)::value;
-          acc[rt][q] = mfma32(Rp[q][0], Kp[rt][0], acc[rt][q]);
-          acc[rt][q] = mfma32(Rp[q][1], Kp[rt][1], acc[rt][q]);
-        });
+    static_for<2>([&](auto rc) {
+      constexpr int rt = decltype(rc)::value;
+      static_for<NQW>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        acc[rt][q] = mfma32(Rp[q][0], Kp[rt][0], acc[rt][q]);
+        acc[rt][q] = mfma32(Rp[q][1], Kp[rt][1], acc[rt][q]);
       });
-    }
+    });
   };
   auto compute = [&](int buf) __attribute__((always_inline)) {
     const half8* Af = reinterpret_cast<const half8*>(lds + buf * BUF_BYTES);
@@ -838,89 +836,23 @@ __device__ void mkw_tiles(const MkArgs& a, char* lds, const half8* colA_p, const
       constexpr int sl = decltype(sc)::value;
       A[sl] = Af[aidx[sl]];
     });
-    if constexpr (DEFER) {
-      static_for<2>([&](auto rc) {
-        constexpr int rt = decltype(rc)::value;
-        f16v D;
+    static_for<2>([&](auto rc) {
+      constexpr int rt = decltype(rc)::value;
+      f16v D;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) D[r] = 0.0f;
-        static_for<NS>([&](auto sc) {
-          constexpr int sl = decltype(sc)::value;
-          D = mfma32(A[sl], Bfr[rt][sl], D);
-        });
-        static_for<2>([&](auto tc) {
-          constexpr int t = decltype(tc)::value;
-          half8 Kh;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) Kh[j] = (_Float16)kval<KERN>(D[8 * t + j], a.p);
-          Kp[rt][t] = Kh;
-        });
-      });
-    } else {
-      // Interleaved within the wave: row tile 1's distance MFMAs issue beside row tile 0's
-      // exponentials and conversions, and row tile 0's K Z MFMAs beside row tile 1's;
-      // scheduling barriers keep the compiler from regrouping the chunks.  Measured at the
-      // 2M-point, 64-column shape: 7.28 ms per launch against 6.7-6.9 ms for the deferred
-      // form above, which the kernel instantiates.
-      f16v D0, D1;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        D0[r] = 0.0f;
-        D1[r] = 0.0f;
-      }
+      for (int r = 0; r < 16; ++r) D[r] = 0.0f;
       static_for<NS>([&](auto sc) {
         constexpr int sl = decltype(sc)::value;
-        D0 = mfma32(A[sl], Bfr[0][sl], D0);
+        D = mfma32(A[sl], Bfr[rt][sl], D);
       });
-      // eight kernel values of row tile rt, slice t, half h (four values) as float16
-      auto kv4 = [&](const f16v& D, half8& K, int t, int h) __attribute__((always_inline)) {
+      static_for<2>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        half8 Kh;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) K[4 * h + j] = (_Float16)kval<KERN>(D[8 * t + 4 * h + j], a.p);
-      };
-      half8 K00, K01, K10, K11;
-      // distance of row tile 1 (NS MFMAs) beside the 16 kernel values of row tile 0
-      static_for<NS>([&](auto sc) {
-        constexpr int sl = decltype(sc)::value;
-        __builtin_amdgcn_sched_barrier(0);
-        D1 = mfma32(A[sl], Bfr[1][sl], D1);
-        // NS = 2, 3 or 4 MFMAs share the four quarter-slices of row tile 0
-        static_for<4>([&](auto qc) {
-          constexpr int qq = decltype(qc)::value;
-          if constexpr (qq * NS / 4 == sl) {
-            if constexpr (qq < 2) kv4(D0, K00, 0, qq);
-            else kv4(D0, K01, 1, qq - 2);
-          }
-        });
+        for (int j = 0; j < 8; ++j) Kh[j] = (_Float16)kval<KERN>(D[8 * t + j], a.p);
+        Kp[rt][t] = Kh;
       });
-      __builtin_amdgcn_sched_barrier(0);
-      Kp[0][0] = K00;
-      Kp[0][1] = K01;
-      // K Z of row tile 0 (2 NQW MFMAs) beside the kernel values of row tile 1
-      static_for<NQW>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        static_for<2>([&](auto tc) {
-          constexpr int t = decltype(tc)::value;
-          constexpr int slot = 2 * q + t;  // 0 .. 2 NQW - 1
-          __builtin_amdgcn_sched_barrier(0);
-          acc[0][q] = mfma32(Rp[q][t], Kp[0][t], acc[0][q]);
-          static_for<4>([&](auto hc) {
-            constexpr int hh = decltype(hc)::value;
-            if constexpr (hh * (2 * NQW) / 4 == slot) {
-              if constexpr (hh < 2) kv4(D1, K10, 0, hh);
-              else kv4(D1, K11, 1, hh - 2);
-            }
-          });
-        });
-      });
-      __builtin_amdgcn_sched_barrier(0);
-      Kp[1][0] = K10;
-      Kp[1][1] = K11;
-      static_for<NQW>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        acc[1][q] = mfma32(Rp[q][0], Kp[1][0], acc[1][q]);
-        acc[1][q] = mfma32(Rp[q][1], Kp[1][1], acc[1][q]);
-      });
-    }
+    });
   };
 
   if (T0 < T1) {
@@ -983,7 +915,7 @@ __global__ __launch_bounds__(256, 2) void mkw_kernel(MkArgs a) {
   const int64_t T0 = (int64_t)split * a.tiles_per_split;
   int64_t T1 = T0 + a.tiles_per_split;
   if (T1 > a.ntiles) T1 = a.ntiles;
-  mkw_tiles<KS, NS, KERN, NQW, true>(
+  mkw_tiles<KS, NS, KERN, NQW>(
       a, lds, a.colA + prob * a.bs_colA, static_cast<const char*>(a.rhs) + prob * a.bs_rhs,
       a.ridx ? a.ridx + prob * a.bs_ridx : nullptr, rw, T0, T1,
       a.part + prob * a.bs_part + (int64_t)split * a.m * a.k);
