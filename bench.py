@@ -718,7 +718,7 @@ def bench_single_k1(args, torch, binding, inputs):
         "roofline": None if kern_ms <= 0 else {
             "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
             "unit": "Ttranscendental/s", "frac": round(achieved / PEAK_EXP_TPS, 4),
-            "traffic": None, "kernel": "mk_kernel (Step-I product, float32 vector mode)",
+            "traffic": None, "kernel": "mkv_kernel (Step-I product, float32 vector mode, 32x32x16 distances)",
             "kernel_ms": round(kern_ms, 4)},
         "cpu_baseline": None,
     }
@@ -909,7 +909,7 @@ def bench_warm(args, torch, binding, inputs):
                        "residual": "2^17-row estimate" if large else "all rows"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
                      "unit": "Texp/s", "frac": round(achieved / PEAK_EXP_TPS, 4), "traffic": None,
-                     "kernel": "mk_kernel (Step-I product, float32 vector mode)",
+                     "kernel": "mkv_kernel (Step-I product, float32 vector mode, 32x32x16 distances)",
                      "kernel_ms": round(kern_ms, 4)},
         "cpu_baseline": None,
     }
