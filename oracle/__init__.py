@@ -27,6 +27,9 @@ Sketch-and-Project", arXiv 2505.13723):
 
 Parity pins: every function here is checked by ``tests/test_oracle_*.py``
 against something other than itself (library routines, closed forms,
-invariants, brute force).  The one exception is listed as "parity unpinned"
-in the docstring of the function concerned.
+invariants, brute force); the helpers (``kernel_from_sqdist``, the oracle's own
+Cholesky and substitutions, the random-feature cosines and ridge weights) through
+the functions that call them (``kernel_matrix`` against scikit-learn,
+``direct_solve`` against ``scipy.linalg.solve``, ``features`` and ``ridge_mean``
+against their closed forms).  No function is left without a pin.
 """
