@@ -207,25 +207,41 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int
       for (int c = 0; c < 4; ++c) acc[j][c] += a * mv[c];
     }
   }
-  // (every index of acc is a compile-time constant, so the array stays in registers)
+  // Sum each row's 64 lane partials by halving exchanges: at offset 32 a lane keeps the four
+  // rows on its side of the offset and receives its partner's partials of them, then two rows
+  // at 16 and one at 8, so that lane l holds row (l >> 3) & 7 summed over the lanes that share
+  // l's bits 3-5; offsets 4, 2 and 1 finish the sum.  (Every index of acc is a compile-time
+  // constant, so the array stays in registers.)
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int c = 0; c < 4; ++c) {
+    if (c < q) {
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = acc[j][c];
+#pragma unroll
+      for (int lev = 0; lev < 3; ++lev) {
+        const int off = 32 >> lev, m = 4 >> lev;
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+          const double give = upper ? v[i] : v[i + m];
+          const double keep = upper ? v[i + m] : v[i];
+          v[i] = keep + __shfl_xor(give, off);
+        }
+      }
+#pragma unroll
+      for (int off = 4; off > 0; off >>= 1) v[0] += __shfl_xor(v[0], off);
+      acc[0][c] = v[0];
+    }
+  }
+  const int64_t row = rbase + ((lane >> 3) & 7);
+  if ((lane & 7) == 0 && row < rows) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       if (c < q) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc[j][c] += __shfl_xor(acc[j][c], off);
-      }
-    }
-    const int64_t row = rbase + j;
-    if (lane == 0 && row < rows) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (c < q) {
-          double v = acc[j][c];
-          if (E) v += f * E[row * lde + c];
-          out[row * ldo + c] = v;
-        }
+        double v = acc[0][c];
+        if (E) v += f * E[row * lde + c];
+        out[row * ldo + c] = v;
       }
     }
   }
@@ -440,13 +456,12 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
                                                       int64_t rot_cap) {
   raise_wave_priority();
   __shared__ double H[RMAX * (RMAX + 1) / 2];
-  __shared__ unsigned short tab[(RMAX / 2) * (RMAX / 2 + 1) / 2];
   Hg += (int64_t)blockIdx.x * r * r;
   evals += (int64_t)blockIdx.x * r;
   rot += (int64_t)blockIdx.x * rot_cap;
   sc += blockIdx.x;
-  __shared__ double cs_c[RMAX / 2], cs_s[RMAX / 2];
-  __shared__ int pp[RMAX / 2], qq[RMAX / 2];
+  __shared__ double2 cs[RMAX / 2];  // (c, s) of each rotation pair of the step
+  __shared__ int pq[RMAX / 2];      // its indices p | q << 16
   __shared__ int nrot;
   __shared__ double hmax;
   const int tid = threadIdx.x;
@@ -456,14 +471,22 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
   // the padded dummy index (odd r) has a zero row and column and is never rotated
   for (int i = tid; i < rp; i += 1024)
     for (int j = i; j < rp; ++j) H[sym_idx(i, j, rp)] = (i < r && j < r) ? Hg[i * r + j] : 0.0;
-  // table of the pair-of-pairs blocks (a, b), a <= b
-  for (int e = tid; e < nblk; e += 1024) {
-    int a = 0, rem = e;
+  // the pair-of-pairs blocks (a, b), a <= b, of this thread: blocks tid + 1024 u, the same
+  // at every step (a thread without a block u takes (0, 0) and stores nothing for it)
+  constexpr int JB = ((RMAX / 2) * (RMAX / 2 + 1) / 2 + 1023) / 1024;
+  int blk_a[JB], blk_b[JB];
+  bool blk_on[JB];
+#pragma unroll
+  for (int u = 0; u < JB; ++u) {
+    const int e = tid + 1024 * u;
+    int a = 0, rem = e < nblk ? e : 0;
     while (rem >= half - a) {
       rem -= half - a;
       ++a;
     }
-    tab[e] = (unsigned short)((a << 8) | (a + rem));
+    blk_a[u] = a;
+    blk_b[u] = a + rem;
+    blk_on[u] = e < nblk;
   }
   __syncthreads();
   if (tid == 0) {
@@ -494,21 +517,24 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
             atomicAdd(&nrot, 1);
           }
         }
-        cs_c[tid] = c;
-        cs_s[tid] = s;
-        pp[tid] = p;
-        qq[tid] = q;
+        cs[tid] = make_double2(c, s);
+        pq[tid] = p | (q << 16);
         const int64_t slot = ((int64_t)sweep * (rp - 1) + step) * half + tid;
         rot[2 * slot] = c;
         rot[2 * slot + 1] = s;
       }
       __syncthreads();
-      for (int e = tid; e < nblk; e += 1024) {
-        const int a = tab[e] >> 8, bb = tab[e] & 255;
-        const double sa = cs_s[a], sb = cs_s[bb];
+      // one block after the other: its (c, s) pairs and indices in one round of LDS reads, its
+      // four entries in a second (the register budget must leave the kernel room beside the
+      // Step-I product on a CU)
+#pragma unroll
+      for (int u = 0; u < JB; ++u) {
+        if (!blk_on[u]) continue;
+        const double2 csa = cs[blk_a[u]], csb = cs[blk_b[u]];
+        const int pqa = pq[blk_a[u]], pqb = pq[blk_b[u]];
+        const double ca = csa.x, sa = csa.y, cb = csb.x, sb = csb.y;
         if (sa == 0.0 && sb == 0.0) continue;
-        const double ca = cs_c[a], cb = cs_c[bb];
-        const int pa = pp[a], qa = qq[a], pb = pp[bb], qb = qq[bb];
+        const int pa = pqa & 0xffff, qa = pqa >> 16, pb = pqb & 0xffff, qb = pqb >> 16;
         const int i11 = sym_idx(pa, pb, rp), i12 = sym_idx(pa, qb, rp);
         const int i21 = sym_idx(qa, pb, rp), i22 = sym_idx(qa, qb, rp);
         const double h11 = H[i11], h12 = H[i12], h21 = H[i21], h22 = H[i22];
@@ -518,7 +544,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
         // columns: J_b
         const double n11 = cb * r11 - sb * r12, n12 = sb * r11 + cb * r12;
         const double n21 = cb * r21 - sb * r22, n22 = sb * r21 + cb * r22;
-        if (a == bb) {
+        if (blk_a[u] == blk_b[u]) {
           // diagonal block (pa < qa): i12 == i21; the rotation annihilates the off-diagonal entry
           H[i11] = n11;
           H[i12] = sa != 0.0 ? 0.0 : n12;
@@ -541,70 +567,88 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
   if (tid == 0) sc->sweeps = sweeps_used;
 }
 
-// V = J_1 J_2 ... applied to the identity: ACC_ROWS rows of V per workgroup, one thread per
-// (row, pair); the rotations of ACC_STEPS steps are staged in LDS at a time.  Rows are
-// independent, so workgroup barriers are needed only around the staging.
-constexpr int ACC_ROWS_MAX = 16;
-// threads per row of V: the rotation pairs (r/2), rounded up to 16, 32 or 64
-__host__ __device__ inline int acc_threads_per_row(int r) {
-  const int half = (r + 1) / 2;
-  return half <= 16 ? 16 : (half <= 32 ? 32 : 64);
-}
-__global__ __launch_bounds__(256) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
-                                                           const IterScalars* __restrict__ sc,
-                                                           double* __restrict__ V, int64_t rot_cap) {
+// V = J_1 J_2 ... applied to the identity.  Rows of V are independent; one wave carries
+// ACC_RPW rows in registers.  Lane k holds, for each of its rows, the two entries that
+// rotation pair k mixes at the current step: seat k and seat rp - 1 - k of the round-robin
+// schedule (index rr_index(seat, step)).  After every step the schedule moves each index
+// by one seat among seats 1 .. rp - 1 (seat 0 stays), i.e. the first entries shift down
+// by one lane and the second entries up by one lane, with the two ends exchanged; after
+// whole sweeps the indices are back at their step-0 seats.
+constexpr int ACC_RPW = 2;    // rows of V per wave
+constexpr int ACC_PF = 8;     // rotation steps loaded ahead
+__global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
+                                                          const IterScalars* __restrict__ sc,
+                                                          double* __restrict__ V, int64_t rot_cap) {
   raise_wave_priority();
   rot += (int64_t)blockIdx.y * rot_cap;
   sc += blockIdx.y;
   V += (int64_t)blockIdx.y * r * r;
-  constexpr int ACC_STEPS = 32;  // rotation steps staged in LDS at a time
-  __shared__ double Vs[ACC_ROWS_MAX][RMAX];
-  __shared__ double R[ACC_STEPS * (RMAX / 2) * 2];
-  const int tid = threadIdx.x;
+  const int k = threadIdx.x;  // rotation pair (lanes >= half hold zeros)
   const int rp = r + (r & 1);
   const int half = rp / 2;
-  const int tpr = acc_threads_per_row(r);  // threads per row: one per rotation pair
-  const int nrows = 256 / tpr;
-  const int row0 = blockIdx.x * nrows;
-  for (int e = tid; e < nrows * RMAX; e += 256) {
-    const int a = e / RMAX, b = e % RMAX;
-    Vs[a][b] = (row0 + a == b) ? 1.0 : 0.0;
+  const int row0 = blockIdx.x * ACC_RPW;
+  const int ia0 = k, ib0 = rp - 1 - k;  // step-0 indices of the two seats of pair k
+  const bool live = k < half;
+  double A[ACC_RPW], Bv[ACC_RPW];
+#pragma unroll
+  for (int j = 0; j < ACC_RPW; ++j) {
+    A[j] = (live && row0 + j == ia0) ? 1.0 : 0.0;
+    Bv[j] = (live && row0 + j == ib0) ? 1.0 : 0.0;
   }
-  const int sweeps = sc->sweeps;
-  const int per_sweep = (rp - 1) * half;
-  const int ir = tid / tpr, k = tid % tpr;
-  for (int sw = 0; sw < sweeps; ++sw) {
-    for (int step = 0; step < rp - 1; ++step) {
-      const int ls = step % ACC_STEPS;
-      if (ls == 0) {
-        // stage the rotations of steps [step, step + ACC_STEPS) of this sweep
-        __syncthreads();
-        const int nst = (rp - 1 - step) < ACC_STEPS ? (rp - 1 - step) : ACC_STEPS;
-        const int64_t base = ((int64_t)sw * per_sweep + (int64_t)step * half) * 2;
-        for (int e = tid; e < 2 * nst * half; e += 256) R[e] = rot[base + e];
-        __syncthreads();
-      }
-      if (k < half && row0 + ir < r) {
-        const double s = R[2 * (ls * half + k) + 1];
-        if (s != 0.0) {
-          const double c = R[2 * (ls * half + k)];
-          const int a = rr_index(k, step, rp), b = rr_index(rp - 1 - k, step, rp);
-          const int p = a < b ? a : b, q = a < b ? b : a;
-          const double vp = Vs[ir][p], vq = Vs[ir][q];
-          Vs[ir][p] = c * vp - s * vq;
-          Vs[ir][q] = s * vp + c * vq;
+  const int steps = sc->sweeps * (rp - 1);
+  // offsets of the two seats in the rotating part: index = 1 + (off + step) mod (rp - 1)
+  int oa = k - 1, ob = rp - 2 - k;
+  const int up = k + 1 < 64 ? k + 1 : 63, dn = k > 0 ? k - 1 : 0;
+  const int kk = live ? k : 0;
+  // ring of the next ACC_PF steps' rotations: slot u holds step g0 + u and is reloaded with
+  // step g0 + u + ACC_PF as soon as it has been used (steps past the end load the last one)
+  double2 ring[ACC_PF];
+  auto load_step = [&](int g) __attribute__((always_inline)) -> double2 {
+    const int gc = g < steps ? g : steps - 1;
+    return reinterpret_cast<const double2*>(rot)[(int64_t)gc * half + kk];
+  };
+  if (steps > 0) {
+#pragma unroll
+    for (int u = 0; u < ACC_PF; ++u) ring[u] = load_step(u);
+  }
+  for (int g0 = 0; g0 < steps; g0 += ACC_PF) {
+#pragma unroll
+    for (int u = 0; u < ACC_PF; ++u) {
+      if (g0 + u < steps) {
+        const double c = ring[u].x, s = ring[u].y;
+        ring[u] = load_step(g0 + u + ACC_PF);
+        // indices of the two seats at this step (seat 0 is index 0 throughout)
+        const int a = k == 0 ? 0 : 1 + oa, b = 1 + ob;
+        const bool aq = a > b;  // the first seat holds q
+        if (live && s != 0.0) {
+#pragma unroll
+          for (int j = 0; j < ACC_RPW; ++j) {
+            const double vp = aq ? Bv[j] : A[j], vq = aq ? A[j] : Bv[j];
+            const double np = c * vp - s * vq, nq = s * vp + c * vq;
+            A[j] = aq ? nq : np;
+            Bv[j] = aq ? np : nq;
+          }
         }
+#pragma unroll
+        for (int j = 0; j < ACC_RPW; ++j) {
+          const double tA = __shfl(A[j], up), tB = __shfl(Bv[j], dn);
+          const double nA = k == 0 ? A[j] : (k < half - 1 ? tA : Bv[j]);
+          const double nB = k == 0 ? (half > 1 ? tA : Bv[j]) : tB;
+          A[j] = nA;
+          Bv[j] = nB;
+        }
+        oa = oa + 1 == rp - 1 ? 0 : oa + 1;
+        ob = ob + 1 == rp - 1 ? 0 : ob + 1;
       }
-      // the threads of one row of V lie in one wave (threads per row divide 64), and the next
-      // step reads only that row, written by that wave, whose LDS operations take effect in
-      // program order: a compiler barrier is enough between steps
-      asm volatile("" ::: "memory");
     }
   }
-  __syncthreads();
-  for (int e = tid; e < nrows * r; e += 256) {
-    const int a = e / r, b = e % r;
-    if (row0 + a < r) V[(int64_t)(row0 + a) * r + b] = Vs[a][b];
+#pragma unroll
+  for (int j = 0; j < ACC_RPW; ++j) {
+    const int row = row0 + j;
+    if (live && row < r) {
+      if (ia0 < r) V[(int64_t)row * r + ia0] = A[j];
+      if (ib0 < r) V[(int64_t)row * r + ib0] = Bv[j];
+    }
   }
 }
 
@@ -770,9 +814,11 @@ adasap_status_t gram(int64_t rows, int p, int q, const void* A, DT at, int64_t l
     ADASAP_LAUNCH_CHECK();
     return ADASAP_OK;
   }
-  // row splits: about 256 workgroups per launch, at least 64 rows each
+  // row splits: about 256 workgroups per launch (it runs beside the Step-I product), or 2048
+  // for a batch (eight per CU, since a batch's Grams run alone), at least 64 rows each
   const int tiles = ((q + G_T - 1) / G_T) * ((p + G_T - 1) / G_T);
-  int64_t want = (256 + (int64_t)tiles * NP - 1) / ((int64_t)tiles * NP);
+  const int64_t target = NP > 1 ? 2048 : 256;
+  int64_t want = (target + (int64_t)tiles * NP - 1) / ((int64_t)tiles * NP);
   const int64_t most = (rows + 63) / 64;
   if (want > most) want = most;
   if (want < 1) want = 1;
@@ -842,9 +888,8 @@ adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, dou
   const int64_t cap = (int64_t)jacobi_rot_capacity(r);
   hipLaunchKernelGGL(jacobi_kernel, dim3(P), dim3(1024), 0, s, r, H, evals, rot_buf, sc, cap);
   ADASAP_LAUNCH_CHECK();
-  const int acc_rows = 256 / acc_threads_per_row(r);
-  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + acc_rows - 1) / acc_rows, P), dim3(256), 0, s,
-                     r, rot_buf, sc, V, cap);
+  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_RPW - 1) / ACC_RPW, P), dim3(64), 0, s, r,
+                     rot_buf, sc, V, cap);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
