@@ -367,8 +367,7 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
       epp.bsE1 = b;
       ADASAP_TRY(mfma_batch_block_product(bp, B, b, colsB.p, wv, 1, mfma_mode_f32v(), u, epp, w2, s2));
       ADASAP_TRY(isqrt(u, z));
-      ADASAP_TRY(dots_vz(b, v, z, sc, pd, s2, P));
-      ADASAP_TRY(normalize_into(b, z, v, sc, i == cfg->power_iters - 1 ? 1 : 0, s2, P));
+      ADASAP_TRY(dots_normalize(b, z, v, sc, i == cfg->power_iters - 1 ? 1 : 0, s2, P));
     }
     ADASAP_HIP(hipEventRecord(ev_join, s2));
     ADASAP_HIP(hipStreamWaitEvent(s, ev_join, 0));

@@ -106,13 +106,10 @@ adasap_status_t nys_finalize(int r, const double* evals, const double* V, int rh
 adasap_status_t woodbury_coefs(int r, const double* S, double rho, int power, double* coefs,
                                IterScalars* sc, hipStream_t s);
 
-// Vector helpers for randomized powering.
-// dots: sc->rq = v.z, sc->vnorm2 = z.z (float64, fixed-order reduction)
-// Batched over P problems with vectors b apart.
-adasap_status_t dots_vz(int64_t b, const double* v, const double* z, IterScalars* sc,
-                        DevBuf& part, hipStream_t s, int P = 1);
-// v = z / sqrt(sc->vnorm2); if last: sc->lam_hat = sc->rq, sc->eta = 1 / sc->rq
-adasap_status_t normalize_into(int64_t b, const double* z, double* v, IterScalars* sc, int last,
+// Vector helpers for randomized powering, batched over P problems with vectors b apart.
+// sc->rq = v.z, sc->vnorm2 = z.z (float64, fixed-order reduction), then v = z / sqrt(z.z);
+// if last: sc->lam_hat = sc->rq, sc->eta = 1 / sc->rq.  v may equal z.
+adasap_status_t dots_normalize(int64_t b, const double* z, double* v, IterScalars* sc, int last,
                                hipStream_t s, int P = 1);
 // sc->vnorm2 = v.v then v /= sqrt(v.v)
 adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf& part,

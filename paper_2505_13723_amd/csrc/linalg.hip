@@ -567,15 +567,30 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
   if (tid == 0) sc->sweeps = sweeps_used;
 }
 
-// V = J_1 J_2 ... applied to the identity.  Rows of V are independent; one wave carries
-// ACC_RPW rows in registers.  Lane k holds, for each of its rows, the two entries that
-// rotation pair k mixes at the current step: seat k and seat rp - 1 - k of the round-robin
-// schedule (index rr_index(seat, step)).  After every step the schedule moves each index
-// by one seat among seats 1 .. rp - 1 (seat 0 stays), i.e. the first entries shift down
-// by one lane and the second entries up by one lane, with the two ends exchanged; after
-// whole sweeps the indices are back at their step-0 seats.
-constexpr int ACC_RPW = 2;    // rows of V per wave
-constexpr int ACC_PF = 8;     // rotation steps loaded ahead
+// Whole-wave lane shifts of a double (DPP wave_shl:1 / wave_shr:1, vector-ALU moves): lane i
+// receives lane i + 1's value (from_next) or lane i - 1's (from_prev); the end lane keeps its
+// own.
+__device__ inline double from_next(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+__device__ inline double from_prev(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+
+// V = J_1 J_2 ... applied to the identity.  Rows of V are independent; one wave (one
+// workgroup) carries RPW rows in registers.  Lane k holds, for each of its rows, the two
+// entries that rotation pair k mixes at the current step: seat k and seat rp - 1 - k of the
+// round-robin schedule (index rr_index(seat, step)).  After every step the schedule moves each
+// index by one seat among seats 1 .. rp - 1 (seat 0 stays), i.e. the first entries shift down
+// by one lane and the second entries up by one lane, with the two ends exchanged; after whole
+// sweeps the indices are back at their step-0 seats.  Every wave reads the rotation sequence
+// itself, ACC_PF steps ahead of their use.
+constexpr int ACC_PF = 8;
+template <int RPW>
 __global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
                                                           const IterScalars* __restrict__ sc,
                                                           double* __restrict__ V, int64_t rot_cap) {
@@ -586,19 +601,18 @@ __global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* _
   const int k = threadIdx.x;  // rotation pair (lanes >= half hold zeros)
   const int rp = r + (r & 1);
   const int half = rp / 2;
-  const int row0 = blockIdx.x * ACC_RPW;
+  const int row0 = blockIdx.x * RPW;
   const int ia0 = k, ib0 = rp - 1 - k;  // step-0 indices of the two seats of pair k
   const bool live = k < half;
-  double A[ACC_RPW], Bv[ACC_RPW];
+  double A[RPW], Bv[RPW];
 #pragma unroll
-  for (int j = 0; j < ACC_RPW; ++j) {
+  for (int j = 0; j < RPW; ++j) {
     A[j] = (live && row0 + j == ia0) ? 1.0 : 0.0;
     Bv[j] = (live && row0 + j == ib0) ? 1.0 : 0.0;
   }
   const int steps = sc->sweeps * (rp - 1);
   // offsets of the two seats in the rotating part: index = 1 + (off + step) mod (rp - 1)
   int oa = k - 1, ob = rp - 2 - k;
-  const int up = k + 1 < 64 ? k + 1 : 63, dn = k > 0 ? k - 1 : 0;
   const int kk = live ? k : 0;
   // ring of the next ACC_PF steps' rotations: slot u holds step g0 + u and is reloaded with
   // step g0 + u + ACC_PF as soon as it has been used (steps past the end load the last one)
@@ -622,7 +636,7 @@ __global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* _
         const bool aq = a > b;  // the first seat holds q
         if (live && s != 0.0) {
 #pragma unroll
-          for (int j = 0; j < ACC_RPW; ++j) {
+          for (int j = 0; j < RPW; ++j) {
             const double vp = aq ? Bv[j] : A[j], vq = aq ? A[j] : Bv[j];
             const double np = c * vp - s * vq, nq = s * vp + c * vq;
             A[j] = aq ? nq : np;
@@ -630,8 +644,8 @@ __global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* _
           }
         }
 #pragma unroll
-        for (int j = 0; j < ACC_RPW; ++j) {
-          const double tA = __shfl(A[j], up), tB = __shfl(Bv[j], dn);
+        for (int j = 0; j < RPW; ++j) {
+          const double tA = from_next(A[j]), tB = from_prev(Bv[j]);
           const double nA = k == 0 ? A[j] : (k < half - 1 ? tA : Bv[j]);
           const double nB = k == 0 ? (half > 1 ? tA : Bv[j]) : tB;
           A[j] = nA;
@@ -643,7 +657,7 @@ __global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* _
     }
   }
 #pragma unroll
-  for (int j = 0; j < ACC_RPW; ++j) {
+  for (int j = 0; j < RPW; ++j) {
     const int row = row0 + j;
     if (live && row < r) {
       if (ia0 < r) V[(int64_t)row * r + ia0] = A[j];
@@ -708,67 +722,56 @@ __global__ void nys_finalize_kernel(int r, const double* __restrict__ evals,
 }
 
 // ---------------------------------------------------------------- powering reductions
-constexpr int DOT_BLOCK = 256;
-constexpr int DOT_PER_BLOCK = 4096;
-
-__global__ void dots_partial_kernel(int64_t n, const double* __restrict__ v,
-                                    const double* __restrict__ z, double* __restrict__ part) {
+// Randomized powering: v . z and z . z (the Rayleigh quotient and the norm) in one workgroup
+// per problem, in a fixed order (strided partials per thread, then the 64 lanes of each wave,
+// then the waves), then v = z / |z|.  The vectors have one block's b entries, so one launch
+// does what a partial-sum, a final-sum and a scaling launch would.  v and z may be the same
+// vector: every entry is read before the barrier that precedes the writes.
+constexpr int DN_THREADS = 1024;
+__global__ __launch_bounds__(DN_THREADS) void dots_normalize_kernel(int64_t n, const double* z,
+                                                                    double* v,
+                                                                    IterScalars* __restrict__ sc,
+                                                                    int last) {
   raise_wave_priority();
-  __shared__ double s1[DOT_BLOCK], s2[DOT_BLOCK];
-  v += (int64_t)blockIdx.y * n;
-  z += (int64_t)blockIdx.y * n;
-  part += (int64_t)blockIdx.y * 2 * gridDim.x;
-  const int64_t base = (int64_t)blockIdx.x * DOT_PER_BLOCK;
+  __shared__ double wa[DN_THREADS / 64], wb[DN_THREADS / 64];
+  __shared__ double inv_s;
+  z += (int64_t)blockIdx.x * n;
+  v += (int64_t)blockIdx.x * n;
+  sc += blockIdx.x;
+  const int tid = threadIdx.x;
   double a = 0.0, b = 0.0;
-  for (int64_t i = base + threadIdx.x; i < base + DOT_PER_BLOCK && i < n; i += DOT_BLOCK) {
+  for (int64_t i = tid; i < n; i += DN_THREADS) {
     const double zi = z[i];
     a += v[i] * zi;
     b += zi * zi;
   }
-  s1[threadIdx.x] = a;
-  s2[threadIdx.x] = b;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+  }
+  if (tid % 64 == 0) {
+    wa[tid / 64] = a;
+    wb[tid / 64] = b;
+  }
   __syncthreads();
-  for (int w = DOT_BLOCK / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s1[threadIdx.x] += s1[threadIdx.x + w];
-      s2[threadIdx.x] += s2[threadIdx.x + w];
+  if (tid == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < DN_THREADS / 64; ++w) {
+      sa += wa[w];
+      sb += wb[w];
     }
-    __syncthreads();
+    sc->rq = sa;
+    sc->vnorm2 = sb;
+    inv_s = 1.0 / sqrt(sb);
+    if (last) {
+      sc->lam_hat = sa;
+      sc->eta = 1.0 / sa;
+    }
   }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s1[0];
-    part[2 * blockIdx.x + 1] = s2[0];
-  }
-}
-
-__global__ void dots_final_kernel(const double* __restrict__ part, int nblk,
-                                  IterScalars* __restrict__ sc) {
-  raise_wave_priority();
-  if (threadIdx.x != 0) return;
-  part += (int64_t)blockIdx.x * 2 * nblk;
-  sc += blockIdx.x;
-  double a = 0.0, b = 0.0;
-  for (int i = 0; i < nblk; ++i) {
-    a += part[2 * i];
-    b += part[2 * i + 1];
-  }
-  sc->rq = a;
-  sc->vnorm2 = b;
-}
-
-__global__ void normalize_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ v,
-                                 IterScalars* __restrict__ sc, int last) {
-  raise_wave_priority();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  z += (int64_t)blockIdx.y * n;
-  v += (int64_t)blockIdx.y * n;
-  sc += blockIdx.y;
-  const double inv = 1.0 / sqrt(sc->vnorm2);
-  if (i < n) v[i] = z[i] * inv;
-  if (last && i == 0) {
-    sc->lam_hat = sc->rq;
-    sc->eta = 1.0 / sc->rq;
-  }
+  __syncthreads();
+  const double inv = inv_s;
+  for (int64_t i = tid; i < n; i += DN_THREADS) v[i] = z[i] * inv;
 }
 
 __global__ void woodbury_coefs_kernel(int r, const double* __restrict__ S, double rho, int power,
@@ -888,8 +891,15 @@ adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, dou
   const int64_t cap = (int64_t)jacobi_rot_capacity(r);
   hipLaunchKernelGGL(jacobi_kernel, dim3(P), dim3(1024), 0, s, r, H, evals, rot_buf, sc, cap);
   ADASAP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(jacobi_accum_kernel, dim3((r + ACC_RPW - 1) / ACC_RPW, P), dim3(64), 0, s, r,
-                     rot_buf, sc, V, cap);
+  // one wave per RPW rows of V: two rows for one problem (its chain runs beside the Step-I
+  // product, whose waves leave about 280 registers of a SIMD free), eight for a batch (which
+  // runs alone: fewer passes over each problem's rotations)
+  if (P == 1)
+    hipLaunchKernelGGL(jacobi_accum_kernel<2>, dim3((r + 1) / 2, P), dim3(64), 0, s, r, rot_buf,
+                       sc, V, cap);
+  else
+    hipLaunchKernelGGL(jacobi_accum_kernel<8>, dim3((r + 7) / 8, P), dim3(64), 0, s, r, rot_buf,
+                       sc, V, cap);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
@@ -903,31 +913,17 @@ adasap_status_t nys_finalize(int r, const double* evals, const double* V, int rh
   return ADASAP_OK;
 }
 
-adasap_status_t dots_vz(int64_t b, const double* v, const double* z, IterScalars* sc,
-                        DevBuf& part, hipStream_t s, int P) {
-  int nblk = (int)((b + DOT_PER_BLOCK - 1) / DOT_PER_BLOCK);
-  if (nblk < 1) nblk = 1;
-  ADASAP_TRY(part.ensure((size_t)2 * nblk * P * sizeof(double)));
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, P), dim3(DOT_BLOCK), 0, s, b, v, z,
-                     part.as<double>());
-  ADASAP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(dots_final_kernel, dim3(P), dim3(64), 0, s, part.as<double>(), nblk, sc);
-  ADASAP_LAUNCH_CHECK();
-  return ADASAP_OK;
-}
-
-adasap_status_t normalize_into(int64_t b, const double* z, double* v, IterScalars* sc, int last,
-                               hipStream_t s, int P) {
-  hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)((b + 255) / 256), P), dim3(256), 0, s, b, z,
-                     v, sc, last);
-  ADASAP_LAUNCH_CHECK();
-  return ADASAP_OK;
-}
-
 adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf& part,
                                   hipStream_t s, int P) {
-  ADASAP_TRY(dots_vz(b, v, v, sc, part, s, P));
-  return normalize_into(b, v, v, sc, 0, s, P);
+  (void)part;
+  return dots_normalize(b, v, v, sc, 0, s, P);
+}
+
+adasap_status_t dots_normalize(int64_t b, const double* z, double* v, IterScalars* sc, int last,
+                               hipStream_t s, int P) {
+  hipLaunchKernelGGL(dots_normalize_kernel, dim3(P), dim3(DN_THREADS), 0, s, b, z, v, sc, last);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
 }
 
 }  // namespace adasap

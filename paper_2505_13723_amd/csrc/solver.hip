@@ -411,8 +411,7 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
       ADASAP_TRY(precond_apply_h(h, 1, u, z, 1, s2, h->part_g2, h->coef2));
       zin = z;
     }
-    ADASAP_TRY(dots_vz(b, v, zin, sc, h->part_d, s2));
-    ADASAP_TRY(normalize_into(b, zin, v, sc, i == c.power_iters - 1 ? 1 : 0, s2));
+    ADASAP_TRY(dots_normalize(b, zin, v, sc, i == c.power_iters - 1 ? 1 : 0, s2));
   }
   // join: the direction needs both the block gradient and the Nystrom factors
   ADASAP_HIP(hipEventRecord(h->ev_join, s2));
