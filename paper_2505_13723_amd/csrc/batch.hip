@@ -343,22 +343,24 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     ADASAP_TRY(gemm_rm(b, r, r, Bm.as<double>(), nullptr, nullptr, r, T.as<double>(), U.as<double>(),
                        r, nullptr, 0, nullptr, 0, s2,
                        Batch{P, (int64_t)b * r, (int64_t)r * r, (int64_t)b * r, 0, 0}));
-    // P^{-1/2} x for every problem's vector x (P x b)
-    auto isqrt = [&](const double* x, double* out) -> adasap_status_t {
-      ADASAP_TRY(gram(b, r, 1, U.p, DT::F64, r, x, DT::F64, 1, coef2.as<double>(), cisq.as<double>(),
-                      pg2, s2, Batch{P, (int64_t)b * r, (int64_t)b, (int64_t)r, (int64_t)r, 0}));
+    // P^{-1/2} x (power 1) or P^{-1} x (power 0) for every problem's vector x (P x b)
+    auto papply = [&](const double* x, double* out, int power) -> adasap_status_t {
+      ADASAP_TRY(gram(b, r, 1, U.p, DT::F64, r, x, DT::F64, 1, coef2.as<double>(),
+                      power == 0 ? cinv.as<double>() : cisq.as<double>(), pg2, s2,
+                      Batch{P, (int64_t)b * r, (int64_t)b, (int64_t)r, (int64_t)r, 0}));
       return gemm_rm(b, r, 1, U.as<double>(), nullptr, nullptr, r, coef2.as<double>(), out, 1, x, 1,
-                     &sc->rho, 2, s2,
+                     &sc->rho, power == 0 ? 1 : 2, s2,
                      Batch{P, (int64_t)b * r, (int64_t)r, (int64_t)b, (int64_t)b, SC_DOUBLES});
     };
     double* v = vv.as<double>();
     double* wv = ww.as<double>();
     double* u = uu.as<double>();
     double* z = zz.as<double>();
+    // powering carried as w = P^{-1/2} v: one P^{-1} apply per step (power_step)
     ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_POW, 0, b, v, s2, P, t_dev));
     ADASAP_TRY(normalize_inplace(b, v, sc, pd, s2, P));
+    ADASAP_TRY(papply(v, wv, 1));
     for (int i = 0; i < cfg->power_iters; ++i) {
-      ADASAP_TRY(isqrt(v, wv));
       KbEpilogue epp;
       epp.E1 = wv;
       epp.e1t = DT::F64;
@@ -366,8 +368,8 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
       epp.a1 = lam;
       epp.bsE1 = b;
       ADASAP_TRY(mfma_batch_block_product(bp, B, b, colsB.p, wv, 1, mfma_mode_f32v(), u, epp, w2, s2));
-      ADASAP_TRY(isqrt(u, z));
-      ADASAP_TRY(dots_normalize(b, z, v, sc, i == cfg->power_iters - 1 ? 1 : 0, s2, P));
+      ADASAP_TRY(papply(u, z, 0));
+      ADASAP_TRY(power_step(b, wv, u, z, sc, i == cfg->power_iters - 1 ? 1 : 0, s2, P));
     }
     ADASAP_HIP(hipEventRecord(ev_join, s2));
     ADASAP_HIP(hipStreamWaitEvent(s, ev_join, 0));

@@ -111,6 +111,11 @@ adasap_status_t woodbury_coefs(int r, const double* S, double rho, int power, do
 // if last: sc->lam_hat = sc->rq, sc->eta = 1 / sc->rq.  v may equal z.
 adasap_status_t dots_normalize(int64_t b, const double* z, double* v, IterScalars* sc, int last,
                                hipStream_t s, int P = 1);
+// One powering step carried as w = P^{-1/2} v: sc->rq = w.u, sc->vnorm2 = u.y with
+// u = (K + lambda I) w and y = P^{-1} u (y = u without a preconditioner), then w = y / sqrt(u.y);
+// if last: sc->lam_hat = sc->rq, sc->eta = 1 / sc->rq.
+adasap_status_t power_step(int64_t b, double* w, const double* u, const double* y, IterScalars* sc,
+                           int last, hipStream_t s, int P = 1);
 // sc->vnorm2 = v.v then v /= sqrt(v.v)
 adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf& part,
                                   hipStream_t s, int P = 1);

@@ -774,6 +774,58 @@ __global__ __launch_bounds__(DN_THREADS) void dots_normalize_kernel(int64_t n, c
   for (int64_t i = tid; i < n; i += DN_THREADS) v[i] = z[i] * inv;
 }
 
+// One step of randomized powering on M = P^{-1/2} (K + lambda I) P^{-1/2} carried as
+// w = P^{-1/2} v (v the unit iterate): with u = (K + lambda I) w and y = P^{-1} u,
+// v . M v = w . u and |M v|^2 = u . y, and the next w is y / sqrt(u . y) -- the same iterates
+// as applying P^{-1/2} before and after the product, with one Woodbury apply per step instead
+// of two.  One workgroup per problem; the sums in a fixed order as above.  y may equal u.
+__global__ __launch_bounds__(DN_THREADS) void power_step_kernel(int64_t n, double* w,
+                                                                const double* u, const double* y,
+                                                                IterScalars* __restrict__ sc,
+                                                                int last) {
+  raise_wave_priority();
+  __shared__ double wa[DN_THREADS / 64], wb[DN_THREADS / 64];
+  __shared__ double inv_s;
+  w += (int64_t)blockIdx.x * n;
+  u += (int64_t)blockIdx.x * n;
+  y += (int64_t)blockIdx.x * n;
+  sc += blockIdx.x;
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = tid; i < n; i += DN_THREADS) {
+    const double ui = u[i];
+    a += w[i] * ui;
+    b += ui * y[i];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+  }
+  if (tid % 64 == 0) {
+    wa[tid / 64] = a;
+    wb[tid / 64] = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int q = 0; q < DN_THREADS / 64; ++q) {
+      sa += wa[q];
+      sb += wb[q];
+    }
+    sc->rq = sa;
+    sc->vnorm2 = sb;
+    inv_s = 1.0 / sqrt(sb);
+    if (last) {
+      sc->lam_hat = sa;
+      sc->eta = 1.0 / sa;
+    }
+  }
+  __syncthreads();
+  const double inv = inv_s;
+  for (int64_t i = tid; i < n; i += DN_THREADS) w[i] = y[i] * inv;
+}
+
 __global__ void woodbury_coefs_kernel(int r, const double* __restrict__ S, double rho, int power,
                                       double* __restrict__ coefs, IterScalars* __restrict__ sc) {
   const int i = threadIdx.x;
@@ -917,6 +969,13 @@ adasap_status_t normalize_inplace(int64_t b, double* v, IterScalars* sc, DevBuf&
                                   hipStream_t s, int P) {
   (void)part;
   return dots_normalize(b, v, v, sc, 0, s, P);
+}
+
+adasap_status_t power_step(int64_t b, double* w, const double* u, const double* y, IterScalars* sc,
+                           int last, hipStream_t s, int P) {
+  hipLaunchKernelGGL(power_step_kernel, dim3(P), dim3(DN_THREADS), 0, s, b, w, u, y, sc, last);
+  ADASAP_LAUNCH_CHECK();
+  return ADASAP_OK;
 }
 
 adasap_status_t dots_normalize(int64_t b, const double* z, double* v, IterScalars* sc, int last,

@@ -381,37 +381,40 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
     ADASAP_TRY(gemm_rm(b, r, r, h->Bm.as<double>(), nullptr, nullptr, r, h->T.as<double>(),
                        h->U.as<double>(), r, nullptr, 0, nullptr, 0, s2));
   }
-  // step size by randomized powering
+  // step size by randomized powering (Alg. GetStepsize) on P^{-1/2} (K_BB + lambda I) P^{-1/2},
+  // carried as w = P^{-1/2} v: one P^{-1} apply per step (power_step)
   double* v = h->vv.as<double>();
   double* w = h->ww.as<double>();
   double* u = h->uu.as<double>();
   double* z = h->zz.as<double>();
-  if (!exact) ADASAP_TRY(normals_dev(c.seed, PURPOSE_POW + off, (uint64_t)t, b, v, s2));
-  if (!exact) ADASAP_TRY(normalize_inplace(b, v, sc, h->part_d, s2));
-  for (int i = 0; i < (exact ? 0 : c.power_iters); ++i) {
-    const double* win = v;
+  double* wc = v;
+  if (!exact) {
+    ADASAP_TRY(normals_dev(c.seed, PURPOSE_POW + off, (uint64_t)t, b, v, s2));
+    ADASAP_TRY(normalize_inplace(b, v, sc, h->part_d, s2));
     if (nys) {
       ADASAP_TRY(precond_apply_h(h, 1, v, w, 1, s2, h->part_g2, h->coef2));
-      win = w;
+      wc = w;
     }
+  }
+  for (int i = 0; i < (exact ? 0 : c.power_iters); ++i) {
     KbEpilogue epp;
     epp.kscale = c.outputscale;
-    epp.E1 = win;
+    epp.E1 = wc;
     epp.e1t = DT::F64;
     epp.lde1 = 1;
     epp.a1 = c.lambda;
     if (h->use_mfma)
-      ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, win, DT::F64, 1, mfma_mode_f32v(), u,
+      ADASAP_TRY(mfma_product(h->pack, B, b, h->colsB.p, b, wc, DT::F64, 1, mfma_mode_f32v(), u,
                               DT::F64, epp, h->mw2, s2));
     else
-      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->xkt, h->XB.p, win, DT::F64, 1, 1, u,
+      ADASAP_TRY(hk_kblock(h, b, b, h->XB.p, nullptr, h->xkt, h->XB.p, wc, DT::F64, 1, 1, u,
                            DT::F64, 1, epp, kprec, s2, h->part_kb2));
-    const double* zin = u;
+    const double* y = u;
     if (nys) {
-      ADASAP_TRY(precond_apply_h(h, 1, u, z, 1, s2, h->part_g2, h->coef2));
-      zin = z;
+      ADASAP_TRY(precond_apply_h(h, 1, u, z, 0, s2, h->part_g2, h->coef2));
+      y = z;
     }
-    ADASAP_TRY(dots_normalize(b, zin, v, sc, i == c.power_iters - 1 ? 1 : 0, s2));
+    ADASAP_TRY(power_step(b, wc, u, y, sc, i == c.power_iters - 1 ? 1 : 0, s2));
   }
   // join: the direction needs both the block gradient and the Nystrom factors
   ADASAP_HIP(hipEventRecord(h->ev_join, s2));
