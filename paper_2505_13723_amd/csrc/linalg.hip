@@ -500,20 +500,31 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
   for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
     if (tid == 0) nrot = 0;
     __syncthreads();
+    // the pair of rotation thread tid: indices rr_index(tid, step) and rr_index(rp - 1 - tid,
+    // step), i.e. 1 + (offset + step) mod (rp - 1), kept as offsets that advance by one a step
+    int oa = tid - 1, ob = rp - 2 - tid;
     for (int step = 0; step < rp - 1; ++step) {
       if (tid < half) {
-        const int a = rr_index(tid, step, rp), b = rr_index(rp - 1 - tid, step, rp);
+        const int a = tid == 0 ? 0 : 1 + oa, b = 1 + ob;
+        oa = oa + 1 == rp - 1 ? 0 : oa + 1;
+        ob = ob + 1 == rp - 1 ? 0 : ob + 1;
         const int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, s = 0.0;
         if (q < r) {
           const double apq = H[sym_idx(p, q, rp)];
           const double app = H[sym_idx(p, p, rp)], aqq = H[sym_idx(q, q, rp)];
+          // t = tan of the angle that annihilates apq, the root of smaller magnitude of
+          // t^2 + 2 tau t - 1 = 0 with tau = (aqq - app) / (2 apq):
+          // sgn(tau) / (|tau| + sqrt(1 + tau^2)) = 2 |apq| sgn(tau) / (|d| + sqrt(d^2 + 4 apq^2))
+          // with d = aqq - app (one division fewer; sgn(0) = +1).  It is formed whether or not
+          // the rotation is taken, so that the threshold's square root runs beside it.
+          const double d = aqq - app;
+          const double tt = 2.0 * fabs(apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+          const double t = (d == 0.0 || ((d > 0.0) == (apq > 0.0))) ? tt : -tt;
+          const double ct = 1.0 / sqrt(1.0 + t * t);
           if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_floor)) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = fabs(tau) > 1e150 ? 0.5 / tau
-                                               : (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            c = ct;
+            s = t * ct;
             atomicAdd(&nrot, 1);
           }
         }
@@ -581,27 +592,33 @@ __device__ inline double from_prev(double x) {
                           __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
 }
 
-// V = J_1 J_2 ... applied to the identity.  Rows of V are independent; one wave (one
-// workgroup) carries RPW rows in registers.  Lane k holds, for each of its rows, the two
-// entries that rotation pair k mixes at the current step: seat k and seat rp - 1 - k of the
-// round-robin schedule (index rr_index(seat, step)).  After every step the schedule moves each
-// index by one seat among seats 1 .. rp - 1 (seat 0 stays), i.e. the first entries shift down
-// by one lane and the second entries up by one lane, with the two ends exchanged; after whole
-// sweeps the indices are back at their step-0 seats.  Every wave reads the rotation sequence
-// itself, ACC_PF steps ahead of their use.
-constexpr int ACC_PF = 8;
-template <int RPW>
-__global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
-                                                          const IterScalars* __restrict__ sc,
-                                                          double* __restrict__ V, int64_t rot_cap) {
+// V = J_1 J_2 ... applied to the identity.  Rows of V are independent: a workgroup of NW
+// waves takes NW * RPW rows, each wave RPW of them in registers.  Lane k holds, for each of its
+// rows, the two entries that rotation pair k mixes at the current step: seat k and seat
+// rp - 1 - k of the round-robin schedule (index rr_index(seat, step)).  After every step the
+// schedule moves each index by one seat among seats 1 .. rp - 1 (seat 0 stays), i.e. the first
+// entries shift down by one lane and the second entries up by one lane (DPP moves), with the
+// two ends exchanged; after whole sweeps the indices are back at their step-0 seats.  The
+// workgroup reads the rotations once, ACC_CH steps at a time, through two LDS buffers: the
+// next chunk is loaded into registers while the current one is applied, one barrier a chunk.
+constexpr int ACC_CH = 16;
+template <int RPW, int NW>
+__global__ __launch_bounds__(NW * 64) void jacobi_accum_kernel(int r, const double* __restrict__ rot,
+                                                               const IterScalars* __restrict__ sc,
+                                                               double* __restrict__ V,
+                                                               int64_t rot_cap) {
   raise_wave_priority();
+  constexpr int NT = NW * 64;
+  constexpr int PER_T = (ACC_CH * (RMAX / 2) + NT - 1) / NT;  // staged elements per thread
+  __shared__ double2 rb[2][ACC_CH * (RMAX / 2)];
   rot += (int64_t)blockIdx.y * rot_cap;
   sc += blockIdx.y;
   V += (int64_t)blockIdx.y * r * r;
-  const int k = threadIdx.x;  // rotation pair (lanes >= half hold zeros)
+  const int tid = threadIdx.x;
+  const int k = tid % 64;  // rotation pair (lanes >= half hold zeros)
   const int rp = r + (r & 1);
   const int half = rp / 2;
-  const int row0 = blockIdx.x * RPW;
+  const int row0 = (blockIdx.x * NW + tid / 64) * RPW;
   const int ia0 = k, ib0 = rp - 1 - k;  // step-0 indices of the two seats of pair k
   const bool live = k < half;
   double A[RPW], Bv[RPW];
@@ -611,26 +628,44 @@ __global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* _
     Bv[j] = (live && row0 + j == ib0) ? 1.0 : 0.0;
   }
   const int steps = sc->sweeps * (rp - 1);
+  const int per_chunk = ACC_CH * half;
+  const double2* rot2 = reinterpret_cast<const double2*>(rot);
+  double2 nx[PER_T];
+  // element e = tid + NT u of the chunk that starts at step g0 (clamped to the last step)
+  auto fetch = [&](int g0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < PER_T; ++u) {
+      const int e = tid + NT * u;
+      const int ec = e < per_chunk ? e : 0;
+      int g = g0 + ec / half;
+      g = g < steps ? g : steps - 1;
+      nx[u] = rot2[(int64_t)g * half + ec % half];
+    }
+  };
+  auto stage = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < PER_T; ++u) {
+      const int e = tid + NT * u;
+      if (e < per_chunk) rb[buf][e] = nx[u];
+    }
+  };
   // offsets of the two seats in the rotating part: index = 1 + (off + step) mod (rp - 1)
   int oa = k - 1, ob = rp - 2 - k;
   const int kk = live ? k : 0;
-  // ring of the next ACC_PF steps' rotations: slot u holds step g0 + u and is reloaded with
-  // step g0 + u + ACC_PF as soon as it has been used (steps past the end load the last one)
-  double2 ring[ACC_PF];
-  auto load_step = [&](int g) __attribute__((always_inline)) -> double2 {
-    const int gc = g < steps ? g : steps - 1;
-    return reinterpret_cast<const double2*>(rot)[(int64_t)gc * half + kk];
-  };
   if (steps > 0) {
-#pragma unroll
-    for (int u = 0; u < ACC_PF; ++u) ring[u] = load_step(u);
+    fetch(0);
+    stage(0);
   }
-  for (int g0 = 0; g0 < steps; g0 += ACC_PF) {
+  __syncthreads();
+  int cb = 0;
+  for (int g0 = 0; g0 < steps; g0 += ACC_CH) {
+    const bool more = g0 + ACC_CH < steps;
+    if (more) fetch(g0 + ACC_CH);
 #pragma unroll
-    for (int u = 0; u < ACC_PF; ++u) {
+    for (int u = 0; u < ACC_CH; ++u) {
       if (g0 + u < steps) {
-        const double c = ring[u].x, s = ring[u].y;
-        ring[u] = load_step(g0 + u + ACC_PF);
+        const double2 cs2 = rb[cb][u * half + kk];
+        const double c = cs2.x, s = cs2.y;
         // indices of the two seats at this step (seat 0 is index 0 throughout)
         const int a = k == 0 ? 0 : 1 + oa, b = 1 + ob;
         const bool aq = a > b;  // the first seat holds q
@@ -655,6 +690,9 @@ __global__ __launch_bounds__(64) void jacobi_accum_kernel(int r, const double* _
         ob = ob + 1 == rp - 1 ? 0 : ob + 1;
       }
     }
+    if (more) stage(cb ^ 1);
+    __syncthreads();
+    cb ^= 1;
   }
 #pragma unroll
   for (int j = 0; j < RPW; ++j) {
@@ -943,15 +981,15 @@ adasap_status_t jacobi_eig(int r, const double* H, double* evals, double* V, dou
   const int64_t cap = (int64_t)jacobi_rot_capacity(r);
   hipLaunchKernelGGL(jacobi_kernel, dim3(P), dim3(1024), 0, s, r, H, evals, rot_buf, sc, cap);
   ADASAP_LAUNCH_CHECK();
-  // one wave per RPW rows of V: two rows for one problem (its chain runs beside the Step-I
-  // product, whose waves leave about 280 registers of a SIMD free), eight for a batch (which
-  // runs alone: fewer passes over each problem's rotations)
+  // one problem: workgroups of 4 waves x 2 rows spread the rows over many CUs (its chain runs
+  // beside the Step-I product and is latency-bound); a batch: 16 waves x 4 rows, one workgroup
+  // per 64 rows, so that each problem's rotations are read once or twice
   if (P == 1)
-    hipLaunchKernelGGL(jacobi_accum_kernel<2>, dim3((r + 1) / 2, P), dim3(64), 0, s, r, rot_buf,
-                       sc, V, cap);
+    hipLaunchKernelGGL((jacobi_accum_kernel<2, 4>), dim3((r + 7) / 8, P), dim3(256), 0, s, r,
+                       rot_buf, sc, V, cap);
   else
-    hipLaunchKernelGGL(jacobi_accum_kernel<8>, dim3((r + 7) / 8, P), dim3(64), 0, s, r, rot_buf,
-                       sc, V, cap);
+    hipLaunchKernelGGL((jacobi_accum_kernel<4, 16>), dim3((r + 63) / 64, P), dim3(1024), 0, s, r,
+                       rot_buf, sc, V, cap);
   ADASAP_LAUNCH_CHECK();
   return ADASAP_OK;
 }
