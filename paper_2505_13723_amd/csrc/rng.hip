@@ -5,7 +5,6 @@
 //   bounded integer in [0, s): Lemire's multiply-shift with rejection
 //   permutation of [0, m): Fisher-Yates from the top, i swapped with bounded(i + 1)
 #include <algorithm>
-#include <unordered_set>
 #include <vector>
 
 #include "internal.h"
@@ -84,16 +83,46 @@ void sample_block_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n, i
     // draws are still consumed in the oracle's order; the result is all of [0, n)
     return;
   }
-  std::unordered_set<int64_t> chosen;
-  chosen.reserve((size_t)b * 2);
+  // the chosen set: open addressing in a power-of-two table of at least 4b slots (empty = -1),
+  // multiplicative hashing, linear probing; reused across calls of a thread
+  static thread_local std::vector<int64_t> table;
+  size_t cap = 16;
+  while (cap < (size_t)b * 4) cap <<= 1;
+  table.assign(cap, -1);
+  const size_t mask = cap - 1;
+  int shift = 64;
+  for (size_t c = cap; c > 1; c >>= 1) --shift;
+  auto slot = [&](int64_t key) {
+    size_t i = (size_t)(((uint64_t)key * 0x9E3779B97F4A7C15ull) >> shift);
+    while (table[i] != -1 && table[i] != key) i = (i + 1) & mask;
+    return i;
+  };
   int64_t cnt = 0;
   for (int64_t j = n - b; j < n; ++j) {
     const int64_t v = (int64_t)bounded(hs, (uint64_t)j + 1);
-    const int64_t pick = chosen.count(v) ? j : v;
-    chosen.insert(pick);
+    const size_t sv = slot(v);
+    int64_t pick = v;
+    if (table[sv] == v) {
+      pick = j;  // v taken: j itself (never drawn before, since every earlier draw is < j)
+      table[slot(j)] = j;
+    } else {
+      table[sv] = v;
+    }
     out[cnt++] = pick;
   }
-  std::sort(out, out + b);
+  // ascending order: LSD radix sort with 11-bit digits over the bits that [0, n) needs
+  static thread_local std::vector<int64_t> tmp;
+  tmp.resize((size_t)b);
+  int64_t* src = out;
+  int64_t* dst = tmp.data();
+  for (int shift = 0; shift < 63 && ((uint64_t)(n - 1) >> shift) != 0; shift += 11) {
+    int64_t count[2049] = {};
+    for (int64_t i = 0; i < b; ++i) ++count[((src[i] >> shift) & 2047) + 1];
+    for (int d = 0; d < 2048; ++d) count[d + 1] += count[d];
+    for (int64_t i = 0; i < b; ++i) dst[count[(src[i] >> shift) & 2047]++] = src[i];
+    std::swap(src, dst);
+  }
+  if (src != out) std::copy(src, src + b, out);
 }
 
 void permutation_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t m, int64_t* out) {

@@ -419,7 +419,6 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   // join: the direction needs both the block gradient and the Nystrom factors
   ADASAP_HIP(hipEventRecord(h->ev_join, s2));
   ADASAP_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
-  if (prefetch_next) ADASAP_TRY(iter_head(h, t + 1, off));
   // Step IV: direction and update
   const double* Dp = h->G.as<double>();
   if (nys) {
@@ -432,12 +431,16 @@ adasap_status_t iterate(adasap_handle_t h, int64_t t, uint64_t off, const void* 
   }
   if (h->fused) {
     // all-rows and block-row parts of the update in one pass that also packs Z_{t+1}
-    return fused_update(h->pack, h->fu, k, B, b, Dp, sc, h->nc, h->V.as<float>(), h->Z.as<float>(),
-                        Wout, h->dtype, s);
+    ADASAP_TRY(fused_update(h->pack, h->fu, k, B, b, Dp, sc, h->nc, h->V.as<float>(),
+                            h->Z.as<float>(), Wout, h->dtype, s));
+  } else {
+    if (c.accel) ADASAP_TRY(nesterov_dense(n * k, h->V.p, h->Z.p, h->st, h->nc, Wout, h->dtype, s));
+    ADASAP_TRY(nesterov_sparse(b, k, B, Dp, h->V.p, h->Z.p, h->st, h->nc, sc,
+                               c.accel ? Wout : nullptr, h->dtype, s));
   }
-  if (c.accel) ADASAP_TRY(nesterov_dense(n * k, h->V.p, h->Z.p, h->st, h->nc, Wout, h->dtype, s));
-  ADASAP_TRY(nesterov_sparse(b, k, B, Dp, h->V.p, h->Z.p, h->st, h->nc, sc, c.accel ? Wout : nullptr,
-                             h->dtype, s));
+  // the head of the next iteration (host sampling of B_{t+1}, then its second-stream work)
+  // is enqueued after this update, so that the update never waits for the host's sampling
+  if (prefetch_next) ADASAP_TRY(iter_head(h, t + 1, off));
   return ADASAP_OK;
 }
 
