@@ -665,18 +665,17 @@ __global__ __launch_bounds__(NW * 64) void jacobi_accum_kernel(int r, const doub
     for (int u = 0; u < ACC_CH; ++u) {
       if (g0 + u < steps) {
         const double2 cs2 = rb[cb][u * half + kk];
-        const double c = cs2.x, s = cs2.y;
         // indices of the two seats at this step (seat 0 is index 0 throughout)
         const int a = k == 0 ? 0 : 1 + oa, b = 1 + ob;
-        const bool aq = a > b;  // the first seat holds q
-        if (live && s != 0.0) {
+        // the rotation (v_p, v_q) <- (c v_p - s v_q, s v_p + c v_q) with the first seat holding
+        // p (a < b) or q: A <- c A + s' B, B <- c B - s' A with s' = -s or +s.  A step without a
+        // rotation has c = 1, s = 0 and leaves both unchanged.
+        const double c = cs2.x, sf = a > b ? cs2.y : -cs2.y;
 #pragma unroll
-          for (int j = 0; j < RPW; ++j) {
-            const double vp = aq ? Bv[j] : A[j], vq = aq ? A[j] : Bv[j];
-            const double np = c * vp - s * vq, nq = s * vp + c * vq;
-            A[j] = aq ? nq : np;
-            Bv[j] = aq ? np : nq;
-          }
+        for (int j = 0; j < RPW; ++j) {
+          const double na = c * A[j] + sf * Bv[j], nb = c * Bv[j] - sf * A[j];
+          A[j] = na;
+          Bv[j] = nb;
         }
 #pragma unroll
         for (int j = 0; j < RPW; ++j) {

@@ -117,3 +117,35 @@ def test_powering_with_exact_preconditioner_gives_one():
         lambda v: H @ v, lambda v: nys.precond_inv_sqrt(U, S, rho, v),
         np.random.default_rng(16).standard_normal(50))
     assert abs(lam_hat - 1.0) < 1e-12 and abs(eta - 1.0) < 1e-12
+
+
+def test_powering_carried_as_preconditioned_vector_matches_printed_form():
+    """The GPU's powering keeps w = P^{-1/2} v: u = H w, y = P^{-1} u, v.(M v) = w.u,
+    |M v|^2 = u.y and the next w = y / sqrt(u.y) for M = P^{-1/2} H P^{-1/2}.  In exact
+    arithmetic these are the printed iterates; here both forms run on the same sketch and
+    start, and the Rayleigh quotients agree to rounding at every step."""
+    rs = np.random.default_rng(11)
+    b, d, r, lam = 300, 4, 40, 1e-2
+    X = rs.standard_normal((b, d))
+    H = K.kernel_matrix(X, X, K.RBF, 0.8) + lam * np.eye(b)
+    Om = rs.standard_normal((b, r))
+    U, S, _ = nys.nystrom(H @ Om, Om)
+    rho = lam + S[-1]
+    v0 = rs.standard_normal(b)
+    v = v0 / np.linalg.norm(v0)
+    w = nys.precond_inv_sqrt(U, S, rho, v)
+    for _ in range(10):
+        # printed form
+        z = nys.precond_inv_sqrt(U, S, rho, H @ nys.precond_inv_sqrt(U, S, rho, v))
+        rq_printed = float(v @ z)
+        v = z / np.linalg.norm(z)
+        # carried form
+        u = H @ w
+        y = nys.precond_inv(U, S, rho, u)
+        rq_carried = float(w @ u)
+        w = y / np.sqrt(float(u @ y))
+        assert rq_carried == pytest.approx(rq_printed, rel=1e-12)
+    np.testing.assert_allclose(w, nys.precond_inv_sqrt(U, S, rho, v), rtol=0, atol=1e-12)
+    eta, lam_hat = stepsize.preconditioned_stepsize(
+        lambda x: H @ x, lambda x: nys.precond_inv_sqrt(U, S, rho, x), v0)
+    assert rq_carried == pytest.approx(lam_hat, rel=1e-12)
