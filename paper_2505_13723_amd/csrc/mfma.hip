@@ -1036,16 +1036,45 @@ __device__ void mkv_tiles(const MkArgs& a, char* lds, const half8* colA_p, const
         D[rt] = mfma32(A[sl], Bfr[rt][sl], D[rt]);
       });
     });
-    static_for<2>([&](auto rc) {
-      constexpr int rt = decltype(rc)::value;
-      float kv[16];
+    if constexpr (KC == 1 && (KERN == ADASAP_MATERN32 || KERN == ADASAP_MATERN52)) {
+      // One right-hand side: the Matern polynomial is folded into the product.  With
+      // u = a log2(e) (a = p r / ell) and e = 2^-u, k z = e (1 + a) z = e (z + u (ln2 z)) for
+      // 3/2 and e (z + u (ln2 z + u (ln2^2 / 3) z)) for 5/2; the column factors are formed
+      // once per tile, so a pair costs the two transcendentals, one multiply and two or three
+      // fmas instead of the polynomial's multiplies and adds and the product's fma.
+      constexpr float LN2 = 0.6931471805599453f;
+      float z1[16], z2[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) kv[r] = kval<KERN>(D[rt][r], a.p);
+      for (int r = 0; r < 16; ++r) {
+        z1[r] = LN2 * zc[r][0];
+        z2[r] = (LN2 * LN2 / 3.0f) * zc[r][0];
+      }
+      const float pl = a.p * 1.4426950408889634f;
+      static_for<2>([&](auto rc) {
+        constexpr int rt = decltype(rc)::value;
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
+        for (int r = 0; r < 16; ++r) {
+          // the hardware square root of |s| as in kval
+          const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(D[rt][r])) * pl;
+          const float e = __builtin_amdgcn_exp2f(-u);
+          float t;
+          if constexpr (KERN == ADASAP_MATERN32) t = __builtin_fmaf(u, z1[r], zc[r][0]);
+          else t = __builtin_fmaf(u, __builtin_fmaf(u, z2[r], z1[r]), zc[r][0]);
+          acc[rt][0] = __builtin_fmaf(e, t, acc[rt][0]);
+        }
+      });
+    } else {
+      static_for<2>([&](auto rc) {
+        constexpr int rt = decltype(rc)::value;
+        float kv[16];
 #pragma unroll
-        for (int c = 0; c < KC; ++c) acc[rt][c] = __builtin_fmaf(kv[r], zc[r][c], acc[rt][c]);
-    });
+        for (int r = 0; r < 16; ++r) kv[r] = kval<KERN>(D[rt][r], a.p);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+#pragma unroll
+          for (int c = 0; c < KC; ++c) acc[rt][c] = __builtin_fmaf(kv[r], zc[r][c], acc[rt][c]);
+      });
+    }
   };
 
   if (T0 < T1) {
