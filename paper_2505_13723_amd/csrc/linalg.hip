@@ -449,6 +449,41 @@ __device__ inline int sym_idx(int i, int j, int rp) {
   return i * rp - (i * (i + 1)) / 2 + j;
 }
 
+// The 2x2-block update J_a^T H J_b of the block of rotation pairs (a, b): rows mixed by
+// (ca, sa), then columns by (cb, sb).
+__device__ inline void jac_block(double ca, double sa, double cb, double sb, double h11, double h12,
+                                 double h21, double h22, double& n11, double& n12, double& n21,
+                                 double& n22) {
+  const double r11 = ca * h11 - sa * h21, r12 = ca * h12 - sa * h22;
+  const double r21 = sa * h11 + ca * h21, r22 = sa * h12 + ca * h22;
+  n11 = cb * r11 - sb * r12;
+  n12 = sb * r11 + cb * r12;
+  n21 = cb * r21 - sb * r22;
+  n22 = sb * r21 + cb * r22;
+}
+
+// The rotation (c, s) that annihilates apq, or (1, 0) below the threshold (returns whether it
+// rotates).  t = tan of the angle, the root of smaller magnitude of t^2 + 2 tau t - 1 = 0 with
+// tau = (aqq - app) / (2 apq): sgn(tau) / (|tau| + sqrt(1 + tau^2))
+// = 2 |apq| sgn(tau) / (|d| + sqrt(d^2 + 4 apq^2)) with d = aqq - app (one division fewer;
+// sgn(0) = +1).  It is formed whether or not the rotation is taken, so that the threshold's
+// square root runs beside it.
+__device__ inline bool jac_rotation(double apq, double app, double aqq, double abs_floor, double& c,
+                                    double& s) {
+  const double d = aqq - app;
+  const double tt = 2.0 * fabs(apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+  const double t = (d == 0.0 || ((d > 0.0) == (apq > 0.0))) ? tt : -tt;
+  const double ct = 1.0 / sqrt(1.0 + t * t);
+  if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_floor)) {
+    c = ct;
+    s = t * ct;
+    return true;
+  }
+  c = 1.0;
+  s = 0.0;
+  return false;
+}
+
 __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __restrict__ Hg,
                                                       double* __restrict__ evals,
                                                       double* __restrict__ rot,
@@ -513,20 +548,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
         if (q < r) {
           const double apq = H[sym_idx(p, q, rp)];
           const double app = H[sym_idx(p, p, rp)], aqq = H[sym_idx(q, q, rp)];
-          // t = tan of the angle that annihilates apq, the root of smaller magnitude of
-          // t^2 + 2 tau t - 1 = 0 with tau = (aqq - app) / (2 apq):
-          // sgn(tau) / (|tau| + sqrt(1 + tau^2)) = 2 |apq| sgn(tau) / (|d| + sqrt(d^2 + 4 apq^2))
-          // with d = aqq - app (one division fewer; sgn(0) = +1).  It is formed whether or not
-          // the rotation is taken, so that the threshold's square root runs beside it.
-          const double d = aqq - app;
-          const double tt = 2.0 * fabs(apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
-          const double t = (d == 0.0 || ((d > 0.0) == (apq > 0.0))) ? tt : -tt;
-          const double ct = 1.0 / sqrt(1.0 + t * t);
-          if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_floor)) {
-            c = ct;
-            s = t * ct;
-            atomicAdd(&nrot, 1);
-          }
+          if (jac_rotation(apq, app, aqq, abs_floor, c, s)) atomicAdd(&nrot, 1);
         }
         cs[tid] = make_double2(c, s);
         pq[tid] = p | (q << 16);
@@ -548,13 +570,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int r, const double* __res
         const int pa = pqa & 0xffff, qa = pqa >> 16, pb = pqb & 0xffff, qb = pqb >> 16;
         const int i11 = sym_idx(pa, pb, rp), i12 = sym_idx(pa, qb, rp);
         const int i21 = sym_idx(qa, pb, rp), i22 = sym_idx(qa, qb, rp);
-        const double h11 = H[i11], h12 = H[i12], h21 = H[i21], h22 = H[i22];
-        // rows: J_a^T
-        const double r11 = ca * h11 - sa * h21, r12 = ca * h12 - sa * h22;
-        const double r21 = sa * h11 + ca * h21, r22 = sa * h12 + ca * h22;
-        // columns: J_b
-        const double n11 = cb * r11 - sb * r12, n12 = sb * r11 + cb * r12;
-        const double n21 = cb * r21 - sb * r22, n22 = sb * r21 + cb * r22;
+        double n11, n12, n21, n22;
+        jac_block(ca, sa, cb, sb, H[i11], H[i12], H[i21], H[i22], n11, n12, n21, n22);
         if (blk_a[u] == blk_b[u]) {
           // diagonal block (pa < qa): i12 == i21; the rotation annihilates the off-diagonal entry
           H[i11] = n11;
