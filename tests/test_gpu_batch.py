@@ -30,9 +30,12 @@ def _knorm_diff(X, W1, W2, y, ell, lam):
     return np.linalg.norm(OK.kernel_matmul(X, X, E, OK.RBF, ell) + lam * E) / np.linalg.norm(y)
 
 
-def test_batch_matches_oracle_and_single_solves(lib):
+@pytest.mark.parametrize("r", [32, 37, 80])
+def test_batch_matches_oracle_and_single_solves(lib, r):
+    # r = 37: an odd rank (the eigensolver's padded index); r = 80: more than 64 rows of
+    # eigenvectors per problem (two workgroups of the batched accumulation)
     Xs, Ys = _problems()
-    lam, b, r, T, seed = 2e-2, 256, 32, 12, 40
+    lam, b, T, seed = 2e-2, 256, 12, 40
     cfg = lib.config(kernel="rbf", lam=lam, block_size=b, rank=r, max_iters=T, seed=seed,
                      precision="fp32", tol=1e-9)
     Xd = [torch.as_tensor(X, dtype=torch.float32).cuda() for X in Xs]
