@@ -77,7 +77,7 @@ def test_kblock_empty_columns(lib):
     assert out.shape == (4, 2) and torch.all(out == 0)
 
 
-@pytest.mark.parametrize("b,r", [(200, 30), (257, 64), (128, 128), (64, 1), (300, 101)])
+@pytest.mark.parametrize("b,r", [(200, 30), (257, 64), (128, 128), (64, 1), (64, 2), (64, 3), (300, 101)])
 def test_nystrom_matches_oracle(lib, b, r):
     X = np.random.default_rng(b + r).standard_normal((b, 4))
     M = OK.kernel_matrix(X, X, OK.RBF, 1.2)
