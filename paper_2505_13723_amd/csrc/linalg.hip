@@ -166,7 +166,10 @@ __global__ __launch_bounds__(256) void gramv_partial_kernel(int64_t rows, int p,
 
 // OUT = f E + A M for a thin M (q <= 4): 32 rows of A (p <= 128 entries) per workgroup, 8 per
 // wave with their loads in flight together (M staged in LDS once per workgroup)
+// (QM: the largest q of the instantiation; q = 1, the powering and single right-hand-side
+// directions, keeps 8 accumulators instead of 32 and so more waves in flight)
 constexpr int GEMV_ROWS = 32;
+template <int QM>
 __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int q,
                                                         const double* __restrict__ A, int64_t lda,
                                                         const double* __restrict__ M,
@@ -190,21 +193,21 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int
   else if (alpha_mode == 2) f = 1.0 / sqrt(*alpha_ptr);
   // each wave takes 8 consecutive rows and issues their loads together
   const int64_t rbase = (int64_t)blockIdx.x * GEMV_ROWS + (threadIdx.x / 64) * 8;
-  double acc[8][4];
+  double acc[8][QM];
 #pragma unroll
   for (int j = 0; j < 8; ++j)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[j][c] = 0.0;
+    for (int c = 0; c < QM; ++c) acc[j][c] = 0.0;
   for (int l = lane; l < p; l += 64) {
-    double mv[4];
+    double mv[QM];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) mv[c] = c < q ? Ms[l * q + c] : 0.0;
+    for (int c = 0; c < QM; ++c) mv[c] = c < q ? Ms[l * q + c] : 0.0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int64_t row = rbase + j;
       const double a = row < rows ? A[row * lda + l] : 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[j][c] += a * mv[c];
+      for (int c = 0; c < QM; ++c) acc[j][c] += a * mv[c];
     }
   }
   // Sum each row's 64 lane partials by halving exchanges: at offset 32 a lane keeps the four
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int
   // l's bits 3-5; offsets 4, 2 and 1 finish the sum.  (Every index of acc is a compile-time
   // constant, so the array stays in registers.)
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < QM; ++c) {
     if (c < q) {
       double v[8];
 #pragma unroll
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int64_t rows, int p, int
   const int64_t row = rbase + ((lane >> 3) & 7);
   if ((lane & 7) == 0 && row < rows) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < QM; ++c) {
       if (c < q) {
         double v = acc[0][c];
         if (E) v += f * E[row * lde + c];
@@ -952,8 +955,13 @@ adasap_status_t gemm_rm(int64_t rows, int p, int q, const double* A, const doubl
                         int alpha_mode, hipStream_t s, const Batch& bat) {
   if (rows <= 0) return ADASAP_OK;
   if (q <= 4 && p <= 128 && A2 == nullptr) {
-    hipLaunchKernelGGL(gemv_rows_kernel, dim3((unsigned)((rows + GEMV_ROWS - 1) / GEMV_ROWS), bat.P), dim3(256), 0, s,
-                       rows, p, q, A, lda, M, out, ldo, E, lde, alpha_ptr, alpha_mode, bat);
+    const dim3 grid((unsigned)((rows + GEMV_ROWS - 1) / GEMV_ROWS), bat.P);
+    if (q == 1)
+      hipLaunchKernelGGL(gemv_rows_kernel<1>, grid, dim3(256), 0, s, rows, p, q, A, lda, M, out, ldo,
+                         E, lde, alpha_ptr, alpha_mode, bat);
+    else
+      hipLaunchKernelGGL(gemv_rows_kernel<4>, grid, dim3(256), 0, s, rows, p, q, A, lda, M, out, ldo,
+                         E, lde, alpha_ptr, alpha_mode, bat);
     ADASAP_LAUNCH_CHECK();
     return ADASAP_OK;
   }
