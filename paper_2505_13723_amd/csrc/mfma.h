@@ -82,6 +82,7 @@ struct FusedUpd {
   DevBuf packed;   // float16 Z in the Step-I operand order
   DevBuf scale;    // float[k] power-of-two column scales of the packed Z
   DevBuf part;     // per-workgroup maxima [nwg][2][k] of |V| and |Z|
+  DevBuf dpart;    // per-block column maxima [nblk][k] of |D| (the block's direction)
   int nwg = 0, mode = 0, nq = 0;
   uint32_t stamp = 0;
 };

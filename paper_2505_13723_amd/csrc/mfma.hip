@@ -1501,7 +1501,7 @@ __global__ void pos_scatter_kernel(int64_t b, const int64_t* __restrict__ B, uin
 // state (partials) + coef * eta * max_j |D[j, c]| (a bound on the new |Z|: the all-rows map is a
 // convex combination, the block correction adds at most coef * eta * |D|)
 __global__ __launch_bounds__(256) void fused_scale_kernel(int nwg, int k, const float* __restrict__ part,
-                                                          int64_t b, const double* __restrict__ D,
+                                                          int dblk, const float* __restrict__ dpart,
                                                           const IterScalars* __restrict__ sc,
                                                           double coef, float* __restrict__ scale) {
   __shared__ double red[256];
@@ -1511,8 +1511,11 @@ __global__ __launch_bounds__(256) void fused_scale_kernel(int nwg, int k, const 
     const double a = part[((int64_t)w * 2 + 0) * k + c], z = part[((int64_t)w * 2 + 1) * k + c];
     m = fmax(m, fmax(a, z));
   }
+  // max |D| of the column from the per-block maxima (colmax_partial_kernel: a float bound of
+  // each block's maximum, rounded to nearest; a maximum rounded down by an ulp leaves the
+  // power-of-two scale's factor-4 headroom below the float16 range)
   double dm = 0.0;
-  for (int64_t j = threadIdx.x; j < b; j += 256) dm = fmax(dm, fabs(D[j * k + c]));
+  for (int j = threadIdx.x; j < dblk; j += 256) dm = fmax(dm, (double)dpart[(int64_t)j * k + c]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -2202,8 +2205,17 @@ adasap_status_t fused_update(const MfmaPack& pk, FusedUpd& f, int k, const int64
   ADASAP_LAUNCH_CHECK();
   const double cz = c.accel ? (c.z_uses_v_next ? c.alpha * c.gamma + 1.0 - c.alpha : 1.0 - c.alpha) : 1.0;
   const double coef = c.accel ? (c.gamma > cz ? c.gamma : cz) : 1.0;
-  hipLaunchKernelGGL(fused_scale_kernel, dim3(k), dim3(256), 0, s, f.nwg, k, f.part.as<float>(), b, D,
-                     sc, coef, f.scale.as<float>());
+  // column maxima of |D| in coalesced row blocks, then the scales
+  const int64_t rpb = colmax_rows_per_block(b);
+  const int dblk = (int)((b + rpb - 1) / rpb);
+  ADASAP_TRY(f.dpart.ensure((size_t)(dblk > 0 ? dblk : 1) * k * sizeof(float)));
+  if (dblk > 0) {
+    hipLaunchKernelGGL(colmax_partial_kernel, dim3(dblk), dim3(256), 0, s, D, DT::F64, b, k,
+                       (int64_t)k, f.dpart.as<float>(), rpb);
+    ADASAP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(fused_scale_kernel, dim3(k), dim3(256), 0, s, f.nwg, k, f.part.as<float>(), dblk,
+                     f.dpart.as<float>(), sc, coef, f.scale.as<float>());
   ADASAP_LAUNCH_CHECK();
   if (f.mode == MODE_F16W)
     hipLaunchKernelGGL(nesterov_pack_kernel<true>, dim3(f.nwg), dim3(256), 0, s, pk.n, k, pk.ntiles, V,
