@@ -339,14 +339,12 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
     sc += blockIdx.x;
   }
   __shared__ double xt[RMAX];
-  __shared__ int flag;
   __shared__ double s_delta;
   const int tid = threadIdx.x;
   if (tid == 0) {
     double tr = 0.0;
     for (int i = 0; i < r; ++i) tr += Mo[i * r + i];
     s_delta = eps * tr;
-    flag = 0;
   }
   __syncthreads();
   int ok = 0;
@@ -358,34 +356,41 @@ __global__ __launch_bounds__(1024) void nys_core_kernel(int r, const double* __r
       if (j >= i) C[up_idx(i, j, r)] = 0.5 * (Mo[i * r + j] + Mo[j * r + i]) + delta * Qo[i * r + j];
     }
     __syncthreads();
-    // right-looking Cholesky: C = R^T R, R upper
+    // right-looking Cholesky C = R^T R (R upper), one barrier per column: column kk's
+    // trailing update reads the unscaled row kk (C[i][j] -= C[kk][i] C[kk][j] / piv), and row
+    // kk takes its final values, R[kk][kk] = sqrt(piv) and R[kk][j] = C[kk][j] / R[kk][kk], in
+    // column kk + 1's phase, when no thread reads it any more.  The pivot test is uniform.
+    const int ti = tid / 32, tj = tid % 32;
+    double prev_dk = 0.0;
+    bool bad = false;
     for (int kk = 0; kk < r; ++kk) {
-      if (tid == 0) {
-        const double piv = C[up_idx(kk, kk, r)];
-        if (!(piv > 0.0)) flag = 1;
-        else C[up_idx(kk, kk, r)] = sqrt(piv);
+      const double piv = C[up_idx(kk, kk, r)];
+      if (!(piv > 0.0)) {
+        bad = true;
+        break;
       }
-      __syncthreads();
-      if (flag) break;
-      const double dk = C[up_idx(kk, kk, r)];
-      for (int j = kk + 1 + tid; j < r; j += 1024) C[up_idx(kk, j, r)] /= dk;
-      __syncthreads();
-      const int w = r - kk - 1;
-      for (int e = tid; e < w * w; e += 1024) {
-        const int i = kk + 1 + e / w, j = kk + 1 + e % w;
-        if (j >= i) C[up_idx(i, j, r)] -= C[up_idx(kk, i, r)] * C[up_idx(kk, j, r)];
+      if (kk > 0) {
+        // row kk - 1: last changed by column kk - 2's update
+        if (tid == 0) C[up_idx(kk - 1, kk - 1, r)] = prev_dk;
+        for (int j = kk + tid; j < r; j += 1024) C[up_idx(kk - 1, j, r)] /= prev_dk;
       }
+      const double inv_piv = 1.0 / piv;
+      for (int i = kk + 1 + ti; i < r; i += 32) {
+        const double ci = C[up_idx(kk, i, r)] * inv_piv;
+        for (int j = kk + 1 + tj; j < r; j += 32)
+          if (j >= i) C[up_idx(i, j, r)] -= ci * C[up_idx(kk, j, r)];
+      }
+      prev_dk = sqrt(piv);
       __syncthreads();
     }
-    if (!flag) {
+    if (!bad) {
+      if (tid == 0) C[up_idx(r - 1, r - 1, r)] = prev_dk;
+      __syncthreads();
       ok = 1;
       break;
     }
     __syncthreads();
-    if (tid == 0) {
-      s_delta *= 10.0;
-      flag = 0;
-    }
+    if (tid == 0) s_delta *= 10.0;
     __syncthreads();
   }
   if (tid == 0) {
