@@ -90,7 +90,9 @@ def test_workspace_bytes(hlib):
 
 
 @pytest.mark.parametrize("n,b,t,seed", [(4096, 256, 0, 1), (4096, 256, 199, 1), (1000, 999, 3, 7),
-                                        (50, 50, 0, 2), (2_000_000, 300, 5, 3)])
+                                        (50, 50, 0, 2), (2_000_000, 300, 5, 3),
+                                        (16384, 8192, 2, 11), (100_000_000, 2000, 4, 5),
+                                        (2**40, 500, 1, 9)])
 def test_host_block_sampler_matches_oracle(hlib, n, b, t, seed):
     mine = hlib.sample_block(seed, binding.PURPOSE_B, t, n, b)
     ref = orng.sample_block(seed, t, n, b)
