@@ -69,6 +69,16 @@ PEAK_EXP_TPS = 256 * 4 * 8 * 2.4e9 / 1e12
 # counted KiB of a 1 GiB copy in the same run (2.0 for FETCH_SIZE, which prices the 128-byte
 # reads of gfx950 at 64 bytes, and 1.0 for WRITE_SIZE); profiles/mkw_kernel_rbf_n2m_d11_k64.md
 STEP1_TRAFFIC_BYTES_N2M = 2.118e9
+# the same for the Matern-3/2 Step-I launch at n = 1M, d = 11, b = 8192 (FETCH_SIZE 1.268e5 KiB
+# on average over three launches, WRITE_SIZE 672 KiB); profiles/mkv_kernel_matern32_n1m_d11.md
+MATERN_STEP1_TRAFFIC_BYTES_N1M = 2.603e8
+# and for the persistent batched Step-I launch over the 256 uneven problems (FETCH_SIZE 5.000e5
+# KiB over two rounds, WRITE_SIZE 1.138e4 KiB with 32-tile work items; 64-tile items write half
+# that); profiles/mkq_kernel_batched_256_uneven.md
+BATCHED_STEP1_TRAFFIC_BYTES = 1.036e9
+# and for the 1e8-point RBF Step-I launch, d = 9, b = 32768 (FETCH_SIZE 2.894e7 KiB on average
+# over two launches, WRITE_SIZE 2048 KiB); profiles/mkv_kernel_rbf_n1e8_d9.md
+RBF_N100M_STEP1_TRAFFIC_BYTES = 5.926e10
 
 
 def log(msg):
@@ -86,6 +96,9 @@ def main():
     ap.add_argument("--ttr-rows", default="mixed,fp32,mixed_refine",
                     help="time-to-residual runs: mixed (the headline), fp32, mixed_refine")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end the batched and single-column workloads with a 1 GiB device copy, the "
+                         "copy of known size that scales the HBM byte counters")
     ap.add_argument("--cpu-rows", type=int, default=384, help="oracle block rows per host core")
     ap.add_argument("--workload", choices=["c3", "batched", "warm", "step1", "matern32_n1m", "rbf_n100m",
                                            "bo", "matern32_precision", "tailavg", "batched_ttr", "c1"],
@@ -355,13 +368,16 @@ def bench_batched(args, torch, binding, inputs):
         "config": {"workload": "batched_256_rbf_uneven", "problems": len(ns), "rows": int(ns.sum()),
                    "b": b, "r": r, "lambda": lam, "kernel": "rbf", "precision": "fp32"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
-                     "unit": "Texp/s", "frac": round(achieved / PEAK_EXP_TPS, 4), "traffic": None,
+                     "unit": "Texp/s", "frac": round(achieved / PEAK_EXP_TPS, 4),
+                     "traffic": BATCHED_STEP1_TRAFFIC_BYTES,
                      "kernel": "mkq_kernel (persistent batched Step-I product)",
                      "kernel_ms": round(kern_ms, 4), "algorithmic_exp_per_launch": pairs},
         "autotuner": tuned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.calib_copy:
+        calibration_copy(torch)
 
 
 def bench_matern_precision(args, torch, binding, inputs):
@@ -718,12 +734,25 @@ def bench_single_k1(args, torch, binding, inputs):
         "roofline": None if kern_ms <= 0 else {
             "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_EXP_TPS,
             "unit": "Ttranscendental/s", "frac": round(achieved / PEAK_EXP_TPS, 4),
-            "traffic": None, "kernel": "mkv_kernel (Step-I product, float32 vector mode, 32x32x16 distances)",
+            "traffic": None if prec != "fp32" else (RBF_N100M_STEP1_TRAFFIC_BYTES if big
+                                                     else MATERN_STEP1_TRAFFIC_BYTES_N1M),
+            "kernel": "mkv_kernel (Step-I product, float32 vector mode, 32x32x16 distances)",
             "kernel_ms": round(kern_ms, 4)},
         "cpu_baseline": None,
     }
     line.update(extra)
     print(json.dumps(line), flush=True)
+    if args.calib_copy:
+        calibration_copy(torch)
+
+
+def calibration_copy(torch):
+    """A 1 GiB float32 device copy (torch.clone), the dispatch of known size that the
+    FETCH_SIZE and WRITE_SIZE counters of the same run are scaled by."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    a.clone()
+    torch.cuda.synchronize()
+    del a
 
 
 def bench_step1(args, torch, binding, inputs):
@@ -754,9 +783,7 @@ def bench_step1(args, torch, binding, inputs):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / max(1, args.steps) * 1e3
     h.close()
-    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-    a.clone()
-    torch.cuda.synchronize()
+    calibration_copy(torch)
     flops = float(w["b"]) * w["n"] * (2 * w["d"] + 2 * w["k"])
     print(json.dumps({"metric": "Step-I launch (block gradient) wall time",
                       "value": round(ms, 4), "unit": "ms", "steps": args.steps, "warmup": args.warmup,

@@ -111,6 +111,7 @@ struct MfmaQueue {
   int rows_per_wg = 256;
   int rt = 4;         // row tiles of 16 per wave: 64 rt rows per workgroup (2 or 4)
   int wg_per_cu = 2;  // persistent workgroups per CU (2 or 4)
+  int qbeg[9] = {0};  // item ranges of the eight XCDs
   DevBuf items, item_start, nchunk, counter;
 };
 

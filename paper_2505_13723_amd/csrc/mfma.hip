@@ -391,7 +391,14 @@ __device__ inline float kval(float s, float p) {
 struct MkItem {
   int prob, rw;     // problem and row workgroup
   int64_t T0, T1;   // column tiles [T0, T1) of that problem
+  int slot, pad;    // partial-sum slot: start[prob] + rw * chunks[prob] + T0 / chunk
 };
+
+// the work queue is cut into one contiguous range per XCD; the range counters sit 128 bytes
+// apart
+constexpr int QXCDS = 8;
+constexpr int QCOUNTER_STRIDE = 32;
+static_assert(sizeof(MfmaQueue::qbeg) / sizeof(int) == QXCDS + 1, "one item range per XCD");
 
 struct MkArgs {
   const half8* colA;     // column fragments [ntiles][2][KS][64]
@@ -418,6 +425,7 @@ struct MkArgs {
   int* counter;
   const int64_t* colA_off;  // per problem, half8
   const int64_t* rhs_off;   // per problem, bytes
+  int qbeg[QXCDS + 1];      // items [qbeg[x], qbeg[x + 1]) are drained by the workgroups of XCD x
 };
 
 // row tiles per wave: four (each column fragment read from LDS feeds four row tiles), two
@@ -1135,25 +1143,31 @@ __global__ __launch_bounds__(256, 4) void mkv_kernel(MkArgs a) {
 }
 
 // Persistent work-queue form for a batch of problems with uneven column counts: each
-// workgroup takes (problem, row workgroup, tile range) items from a global counter until the
-// table is exhausted; item i writes its partial sums to part[i][rows of its workgroup][k].
+// workgroup takes (problem, row workgroup, tile range) items from its XCD's counter until that
+// XCD's range of the table is exhausted; an item writes its partial sums to
+// part[slot][rows of its workgroup][k].  Workgroups are placed on the XCDs round-robin, so
+// blockIdx.x % 8 names the XCD, and the items of one tile range (its row workgroups, adjacent
+// in the range) meet in that XCD's L2.  Every range has drainers once the grid holds 8
+// workgroups; the placement only decides locality, not which items run.
 template <int KS, int KERN, int MODE, int NQ, int RT>
 __global__ __launch_bounds__(256, (mk_occupancy<KERN, MODE, NQ>())) void mkq_kernel(MkArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[2 * MkShape<KS, MODE, NQ>::BUF_BYTES];
   __shared__ int s_item;
   constexpr int ROWS = WAVES * RT * 16;
+  const int x = (int)(blockIdx.x % QXCDS);
+  const int beg = a.qbeg[x], end = a.qbeg[x + 1];
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+    if (threadIdx.x == 0) s_item = beg + atomicAdd(a.counter + x * QCOUNTER_STRIDE, 1);
     __syncthreads();
     const int item = s_item;
     __syncthreads();
-    if (item >= a.nitems) break;
+    if (item >= end) break;
     const MkItem it = a.items[item];
     mk_tiles<KS, KERN, MODE, NQ, RT>(
         a, lds, a.colA + a.colA_off[it.prob],
         static_cast<const char*>(a.rhs) + a.rhs_off[it.prob],
         a.ridx + (int64_t)it.prob * a.bs_ridx, it.rw, it.T0, it.T1,
-        a.part + (int64_t)item * ROWS * a.k, (int64_t)it.rw * ROWS);
+        a.part + (int64_t)it.slot * ROWS * a.k, (int64_t)it.rw * ROWS);
   }
 }
 
@@ -1741,7 +1755,11 @@ __global__ void mkq_reduce_kernel(const float* __restrict__ part, const int64_t*
   out[(int64_t)pb * b * k + e] = s;
 }
 
-__global__ void zero_int_kernel(int* p) { *p = 0; }
+// the XCD range counters of a work queue (a kernel, not a memset, so that a captured graph
+// holds no memset node)
+__global__ void zero_queue_counters_kernel(int* p) {
+  if (threadIdx.x < QXCDS) p[threadIdx.x * QCOUNTER_STRIDE] = 0;
+}
 
 // ---------------------------------------------------------------- public launchers
 size_t mfma_pack_bytes(int64_t n, int d, int k) {
@@ -2065,31 +2083,54 @@ adasap_status_t mfma_batch_queue_create(const MfmaBatchPack& bp, int64_t b, int6
   const int P = bp.P;
   const int rows_per_wg = WAVES * rt * 16;
   const int rwg = (int)((b + rows_per_wg - 1) / rows_per_wg);
+  // Partial-sum slots keep the problem-major, row-workgroup-major order that the reduction
+  // reads (start[p] + rw * nc + c).  The queue itself runs tile range by tile range, the row
+  // workgroups of a range adjacent, cut into QXCDS contiguous ranges of about equal tile counts.
   std::vector<MkItem> items;
   std::vector<int64_t> start(P);
   std::vector<int> nch(P);
+  int64_t total_tiles = 0, nslots = 0;
   for (int p = 0; p < P; ++p) {
     const int64_t nt = bp.ntiles[p];
     const int nc = (int)((nt + chunk_tiles - 1) / chunk_tiles);
-    start[p] = (int64_t)items.size();
+    start[p] = nslots;
     nch[p] = nc;
-    for (int rw = 0; rw < rwg; ++rw)
-      for (int c = 0; c < nc; ++c) {
-        MkItem it;
-        it.prob = p;
-        it.rw = rw;
-        it.T0 = (int64_t)c * chunk_tiles;
-        it.T1 = it.T0 + chunk_tiles < nt ? it.T0 + chunk_tiles : nt;
-        items.push_back(it);
-      }
+    nslots += (int64_t)rwg * nc;
+    total_tiles += nt;
   }
+  if (nslots > INT32_MAX) {
+    set_error("batched step I: work queue too long");
+    return ADASAP_ERR_INVALID_ARG;
+  }
+  int qcount[QXCDS] = {0};
+  int64_t done_tiles = 0;
+  for (int p = 0; p < P; ++p) {
+    const int64_t nt = bp.ntiles[p];
+    for (int c = 0; c < nch[p]; ++c) {
+      MkItem it{};
+      it.prob = p;
+      it.T0 = (int64_t)c * chunk_tiles;
+      it.T1 = it.T0 + chunk_tiles < nt ? it.T0 + chunk_tiles : nt;
+      int x = total_tiles > 0 ? (int)(done_tiles * QXCDS / total_tiles) : 0;
+      if (x >= QXCDS) x = QXCDS - 1;
+      done_tiles += it.T1 - it.T0;
+      for (int rw = 0; rw < rwg; ++rw) {
+        it.rw = rw;
+        it.slot = (int)(start[p] + (int64_t)rw * nch[p] + c);
+        items.push_back(it);
+        ++qcount[x];
+      }
+    }
+  }
+  q.qbeg[0] = 0;
+  for (int x = 0; x < QXCDS; ++x) q.qbeg[x + 1] = q.qbeg[x] + qcount[x];
   q.nitems = (int)items.size();
   q.rows_per_wg = rows_per_wg;
   q.rt = rt;
   ADASAP_TRY(q.items.ensure(items.size() * sizeof(MkItem)));
   ADASAP_TRY(q.item_start.ensure((size_t)P * sizeof(int64_t)));
   ADASAP_TRY(q.nchunk.ensure((size_t)P * sizeof(int)));
-  ADASAP_TRY(q.counter.ensure(sizeof(int)));
+  ADASAP_TRY(q.counter.ensure((size_t)QXCDS * QCOUNTER_STRIDE * sizeof(int)));
   ADASAP_HIP(hipMemcpyAsync(q.items.p, items.data(), items.size() * sizeof(MkItem),
                             hipMemcpyHostToDevice, s));
   ADASAP_HIP(hipMemcpyAsync(q.item_start.p, start.data(), (size_t)P * sizeof(int64_t),
@@ -2118,14 +2159,19 @@ adasap_status_t mfma_batch_stepI(const MfmaBatchPack& bp, MfmaQueue& q, const in
   a.counter = q.counter.as<int>();
   a.colA_off = bp.col_off_dev.as<int64_t>();
   a.rhs_off = bp.rhs_off_dev.as<int64_t>();
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, a.counter);
+  for (int x = 0; x <= QXCDS; ++x) a.qbeg[x] = q.qbeg[x];
+  hipLaunchKernelGGL(zero_queue_counters_kernel, dim3(1), dim3(64), 0, s, a.counter);
   ADASAP_LAUNCH_CHECK();
   int dev = 0, cus = 256;
   ADASAP_HIP(hipGetDevice(&dev));
   ADASAP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   // persistent workgroups (two or four per CU, within the launch bounds of four), each
-  // draining the queue
+  // draining its XCD's range of the queue; every range needs at least one workgroup
   const int grid = cus * (q.wg_per_cu == 4 ? 4 : 2);
+  if (grid < QXCDS) {
+    set_error("batched step I: fewer persistent workgroups than queue ranges");
+    return ADASAP_ERR_INVALID_ARG;
+  }
   if (ev0) ADASAP_HIP(hipEventRecord(ev0, s));
   if (q.rt == 2) ADASAP_TRY(mkq_launch<2>(bp.kern, grid, a, s));
   else ADASAP_TRY(mkq_launch<4>(bp.kern, grid, a, s));
