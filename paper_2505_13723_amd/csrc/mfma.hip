@@ -2020,7 +2020,9 @@ adasap_status_t mfma_batch_block_product(const MfmaBatchPack& bp, const int64_t*
   const int RT = rt_of(rd.mode, rd.nq);
   const int rows_per_wg = WAVES * RT * 16;
   const int rwg = (int)((b + rows_per_wg - 1) / rows_per_wg);
-  int splits = (int)((2048 / P + rwg - 1) / rwg);
+  // about 1024 workgroups over the batch: one column split per problem at 256 problems, so
+  // the reduction reads one partial per entry
+  int splits = (int)((1024 / P + rwg - 1) / rwg);
   if (splits > nt) splits = (int)nt;
   if (splits < 1) splits = 1;
   int64_t tps = (nt + splits - 1) / splits;
