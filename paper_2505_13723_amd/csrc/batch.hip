@@ -222,21 +222,22 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
     ADASAP_LAUNCH_CHECK();
   }
   hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, k0 = nullptr, k1 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr, k0 = nullptr, k1 = nullptr;
   ADASAP_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
   ADASAP_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
   ADASAP_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  ADASAP_HIP(hipEventCreateWithFlags(&ev_mid, hipEventDisableTiming));
   ADASAP_HIP(hipEventCreate(&k0));
   ADASAP_HIP(hipEventCreate(&k1));
   struct Cleanup {
     hipStream_t s2;
-    hipEvent_t e[4];
+    hipEvent_t e[5];
     ~Cleanup() {
       if (s2) (void)hipStreamSynchronize(s2), (void)hipStreamDestroy(s2);
       for (hipEvent_t x : e)
         if (x) (void)hipEventDestroy(x);
     }
-  } cleanup{s2, {ev_fork, ev_join, k0, k1}};
+  } cleanup{s2, {ev_fork, ev_join, ev_mid, k0, k1}};
   // two pinned upload slots of Pb + 1 entries: every problem's block, then the iteration
   // counter t (read on the device by the random-number kernels, so that a captured round
   // replays with the current t)
@@ -303,8 +304,11 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
   TuneVal chosen{4, 2, 64};
   int tuned_from_cache = 0;
 
-  // the device work of one round (B_t and t already uploaded); `last` also writes W
-  auto round = [&](bool last, bool timed) -> adasap_status_t {
+  // the device work of one round (B_t and t already uploaded); `last` also writes W.  The
+  // Gaussian test matrices of round t + 1 are drawn during round t, on the main stream beside
+  // the eigensolvers (one workgroup per problem, most of the GPU idle), once the sketch
+  // products and Grams of round t have read those of round t; the first round draws its own.
+  auto round = [&](bool last, bool timed, bool first) -> adasap_status_t {
     const int64_t* B = Bdev.as<int64_t>();
     ADASAP_HIP(hipEventRecord(ev_fork, s));
     ADASAP_HIP(hipStreamWaitEvent(s2, ev_fork, 0));
@@ -325,7 +329,7 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
                                 timed ? k0 : nullptr, timed ? k1 : nullptr));
     // second stream: sketch, Nystrom factors, step size for every problem
     ADASAP_TRY(mfma_batch_pack_blocks(bp, B, b, colsB, s2));
-    ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_OMEGA, 0, b * r, Om.as<double>(), s2, P, t_dev));
+    if (first) ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_OMEGA, 0, b * r, Om.as<double>(), s2, P, t_dev));
     KbEpilogue none;
     ADASAP_TRY(mfma_batch_block_product(bp, B, b, colsB.p, Om.as<double>(), r, mfma_mode_f16x3(),
                                         Ysk.as<double>(), none, w2, s2));
@@ -336,6 +340,8 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
                        Bm.as<double>(), r, nullptr, 0, nullptr, 0, s2,
                        Batch{P, (int64_t)b * r, (int64_t)r * r, (int64_t)b * r, 0, SC_DOUBLES}));
     ADASAP_TRY(gram(b, r, r, Bm.p, DT::F64, r, Bm.p, DT::F64, r, H.as<double>(), nullptr, pg2, s2, bBR));
+    // Om is not read after this point of the round
+    ADASAP_HIP(hipEventRecord(ev_mid, s2));
     ADASAP_TRY(jacobi_eig(r, H.as<double>(), ev.as<double>(), Vr.as<double>(), rot.as<double>(), sc, s2, P));
     ADASAP_TRY(nys_finalize(r, ev.as<double>(), Vr.as<double>(), cfg->rho_rule, lam, cfg->rho,
                             S.as<double>(), T.as<double>(), cinv.as<double>(), cisq.as<double>(),
@@ -372,6 +378,10 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
       ADASAP_TRY(power_step(b, wv, u, z, sc, i == cfg->power_iters - 1 ? 1 : 0, s2, P));
     }
     ADASAP_HIP(hipEventRecord(ev_join, s2));
+    if (!last) {
+      ADASAP_HIP(hipStreamWaitEvent(s, ev_mid, 0));
+      ADASAP_TRY(normals_dev(cfg->seed, PURPOSE_OMEGA, 1, b * r, Om.as<double>(), s, P, t_dev));
+    }
     ADASAP_HIP(hipStreamWaitEvent(s, ev_join, 0));
     // direction and update (main stream)
     ADASAP_TRY(gram(b, r, 1, U.p, DT::F64, r, G.p, DT::F64, 1, coef.as<double>(), cinv.as<double>(),
@@ -451,7 +461,7 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
       if (!graph_exec) {
         // capture this round's device work once; any capture failure leaves the eager rounds
         hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
-        adasap_status_t rst = ce == hipSuccess ? round(false, false) : ADASAP_ERR_DEVICE;
+        adasap_status_t rst = ce == hipSuccess ? round(false, false, false) : ADASAP_ERR_DEVICE;
         hipGraph_t g = nullptr;
         const hipError_t ee = ce == hipSuccess ? hipStreamEndCapture(s, &g) : ce;
         if (rst == ADASAP_OK && ee == hipSuccess && g &&
@@ -465,9 +475,9 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
         }
       }
       if (use_graph) ADASAP_HIP(hipGraphLaunch(graph_exec, s));
-      else ADASAP_TRY(round(false, false));
+      else ADASAP_TRY(round(false, false, false));
     } else {
-      ADASAP_TRY(round(last, true));
+      ADASAP_TRY(round(last, true, t == 0));
       float kms = 0;
       ADASAP_HIP(hipEventSynchronize(k1));
       ADASAP_HIP(hipEventElapsedTime(&kms, k0, k1));

@@ -139,7 +139,7 @@ adasap_status_t pathwise_combine(int64_t m, int k, const void* prior, DT pt, voi
 
 // ---- random numbers (rng.hip) -------------------------------------------------------------
 // Batched over P problems: problem p uses seed + p and writes out + p * count.
-// If t_dev is set, the stream counter is read from device memory (*t_dev) instead of t.
+// If t_dev is set, the stream counter is t + *t_dev, read from device memory at run time.
 adasap_status_t normals_dev(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
                             double* out, hipStream_t s, int P = 1, const int64_t* t_dev = nullptr);
 void sample_block_host(uint64_t seed, uint64_t purpose, uint64_t t, int64_t n, int64_t b,

@@ -17,7 +17,7 @@ namespace {
 __global__ void normals_kernel(uint64_t seed, uint64_t purpose, uint64_t t, int64_t count,
                                double* __restrict__ out, const int64_t* __restrict__ t_dev) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t_dev) t = (uint64_t)*t_dev;  // counter read from device memory (replayable launches)
+  if (t_dev) t += (uint64_t)*t_dev;  // plus a counter in device memory (replayable launches)
   seed += blockIdx.y;  // problem p of a batch draws with seed + p
   out += (int64_t)blockIdx.y * count;
   if (2 * i >= count) return;
