@@ -305,9 +305,10 @@ extern "C" adasap_status_t adasap_solve_batch(const adasap_problem_t* probs, int
   int tuned_from_cache = 0;
 
   // the device work of one round (B_t and t already uploaded); `last` also writes W.  The
-  // Gaussian test matrices of round t + 1 are drawn during round t, on the main stream beside
-  // the eigensolvers (one workgroup per problem, most of the GPU idle), once the sketch
-  // products and Grams of round t have read those of round t; the first round draws its own.
+  // Gaussian test matrices of round t + 1 are drawn during round t on the main stream, off the
+  // chain's critical path, once the sketch products and Grams of round t have read those of
+  // round t (from the eigensolvers on, whose one workgroup per problem leaves most of the GPU
+  // idle); the first round draws its own.
   auto round = [&](bool last, bool timed, bool first) -> adasap_status_t {
     const int64_t* B = Bdev.as<int64_t>();
     ADASAP_HIP(hipEventRecord(ev_fork, s));
