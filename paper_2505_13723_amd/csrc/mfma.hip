@@ -1583,7 +1583,8 @@ __device__ __forceinline__ float nest_elem(float* __restrict__ V, float* __restr
 }
 
 template <bool WIDE>
-__global__ __launch_bounds__(256) void nesterov_pack_kernel(
+// four waves per SIMD (at most 128 registers; the unconstrained kernel took 134, three waves)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void nesterov_pack_kernel(
     int64_t n, int k, int64_t ntiles, float* __restrict__ V, float* __restrict__ Z,
     const int64_t* __restrict__ pos, uint32_t stamp, const double* __restrict__ D,
     const IterScalars* __restrict__ sc, double beta, double gamma, double alpha, int z_next,
