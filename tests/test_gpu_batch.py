@@ -58,6 +58,27 @@ def test_batch_matches_oracle_and_single_solves(lib, r):
         assert _knorm_diff(Xs[p], Wb, Ws.cpu().double().numpy(), Ys[p], ell, lam) <= 1e-3
 
 
+def test_batch_with_fewer_work_items_than_xcds(lib):
+    # one problem of 300 points: a single Step-I work item, so seven of the eight per-XCD
+    # ranges of the persistent queue are empty; six rounds take the captured-graph path and
+    # the Gaussian test matrices drawn one round ahead
+    n, d, ell = 300, 5, 0.8
+    X, y = inputs.make_c4_problem(3, n, d, seed=11)
+    X = X.astype(np.float32).astype(np.float64)
+    y = y.astype(np.float32).astype(np.float64)
+    lam, b, r, T, seed = 2e-2, 64, 16, 6, 9
+    cfg = lib.config(kernel="rbf", lam=lam, block_size=b, rank=r, max_iters=T, seed=seed,
+                     precision="fp32", tol=1e-9)
+    Xd = [torch.as_tensor(X, dtype=torch.float32).cuda()]
+    Yd = [torch.as_tensor(y, dtype=torch.float32).cuda()]
+    Wd = [torch.zeros_like(Yd[0])]
+    reps = lib.solve_batch(cfg, Xd, Yd, Wd, [ell])
+    Wb = Wd[0].cpu().double().numpy()
+    Wo, info = OA.adasap(X, y, OK.RBF, ell, lam, b, r, T, seed, eps_sketch=2.0**-23)
+    assert _knorm_diff(X, Wb, Wo, y, ell, lam) <= 1e-3
+    assert reps[0]["eta_last"] == pytest.approx(info["eta"][-1], rel=1e-3)
+
+
 def test_batch_rejects_bad_problems(lib):
     Xs, Ys = _problems()
     from paper_2505_13723_amd.binding import AdasapError
