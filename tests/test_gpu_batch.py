@@ -79,6 +79,33 @@ def test_batch_with_fewer_work_items_than_xcds(lib):
     assert reps[0]["eta_last"] == pytest.approx(info["eta"][-1], rel=1e-3)
 
 
+@pytest.mark.parametrize("kind", ["matern12", "matern32", "matern52"])
+def test_batch_matern_kernels_match_oracle(lib, kind):
+    # the batched Step-I queue, sketches and powering products with each Matern kernel
+    # (square root and exponential per pair), three uneven problems
+    sizes = [(900, 4, 0.9), (1300, 10, 1.4), (700, 15, 2.0)]
+    okind = {"matern12": OK.MATERN12, "matern32": OK.MATERN32, "matern52": OK.MATERN52}[kind]
+    lam, b, r, T, seed = 2e-2, 128, 24, 5, 21
+    Xs, Ys = [], []
+    for p, (n, d, ell) in enumerate(sizes):
+        X, y = inputs.make_c4_problem(10 + p, n, d, seed=13)
+        Xs.append(X.astype(np.float32).astype(np.float64))
+        Ys.append(y.astype(np.float32).astype(np.float64))
+    cfg = lib.config(kernel=kind, lam=lam, block_size=b, rank=r, max_iters=T, seed=seed,
+                     precision="fp32", tol=1e-9)
+    Xd = [torch.as_tensor(X, dtype=torch.float32).cuda() for X in Xs]
+    Yd = [torch.as_tensor(y, dtype=torch.float32).cuda() for y in Ys]
+    Wd = [torch.zeros_like(y) for y in Yd]
+    reps = lib.solve_batch(cfg, Xd, Yd, Wd, [s[2] for s in sizes])
+    for p, (n, d, ell) in enumerate(sizes):
+        Wb = Wd[p].cpu().double().numpy()
+        Wo, info = OA.adasap(Xs[p], Ys[p], okind, ell, lam, b, r, T, seed + p, eps_sketch=2.0**-23)
+        E = Wb - Wo
+        delta = np.linalg.norm(OK.kernel_matmul(Xs[p], Xs[p], E, okind, ell) + lam * E) / np.linalg.norm(Ys[p])
+        assert delta <= 1e-3, (kind, p, delta)
+        assert reps[p]["eta_last"] == pytest.approx(info["eta"][-1], rel=1e-3)
+
+
 def test_batch_rejects_bad_problems(lib):
     Xs, Ys = _problems()
     from paper_2505_13723_amd.binding import AdasapError
